@@ -1,0 +1,143 @@
+"""Oracle for the HTM spatial pooler step -- TEST INFRASTRUCTURE ONLY.
+
+ctypes wrapper over ``sp_oracle.c`` (plain C, double-precision permanences),
+a direct implementation of Section 1.1 of Wielgosz & Pietron (arXiv
+1608.01966): Algorithm 1 (overlap), Algorithm 2 (inhibition, global form)
+and the learning rule the paper takes from the Numenta CLA whitepaper.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this module.  The GPU library never does, and this
+module imports nothing from it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "_lib", "libsp_oracle.so")
+
+
+def build() -> str:
+    """Compile the oracle with gcc (portable flags: the library also runs on
+    hosts other than the one that built it)."""
+    os.makedirs(os.path.dirname(_LIB_PATH), exist_ok=True)
+    tmp = _LIB_PATH + ".tmp"
+    subprocess.check_call([
+        "gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-Werror", "-fPIC", "-shared",
+        os.path.join(_HERE, "sp_oracle.c"), "-o", tmp,
+    ])
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class _Cfg(ctypes.Structure):
+    _fields_ = [
+        ("input_bits", ctypes.c_uint32),
+        ("num_columns", ctypes.c_uint32),
+        ("synapses_per_column", ctypes.c_uint32),
+        ("min_overlap", ctypes.c_uint32),
+        ("winners", ctypes.c_uint32),
+        ("connected_perm", ctypes.c_double),
+        ("perm_inc", ctypes.c_double),
+        ("perm_dec", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.c_void_p
+        lib.spo_overlap.argtypes = [ctypes.POINTER(_Cfg), P, P, P, P]
+        lib.spo_overlap.restype = None
+        lib.spo_inhibit.argtypes = [ctypes.POINTER(_Cfg), P, P, P]
+        lib.spo_inhibit.restype = ctypes.c_int
+        lib.spo_learn.argtypes = [ctypes.POINTER(_Cfg), P, P, P, P]
+        lib.spo_learn.restype = None
+        lib.spo_run.argtypes = [ctypes.POINTER(_Cfg), P, P, P, ctypes.c_uint32, ctypes.c_int, P, P]
+        lib.spo_run.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _cfg(cfg: dict) -> _Cfg:
+    """cfg uses the integer 1/256-unit parameters of the library's config."""
+    return _Cfg(
+        int(cfg["input_bits"]), int(cfg["num_columns"]), int(cfg["synapses_per_column"]),
+        int(cfg["min_overlap"]), int(cfg["winners"]),
+        cfg["connected_q8"] / 256.0, cfg["inc_q8"] / 256.0, cfg["dec_q8"] / 256.0,
+    )
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _words(cfg) -> int:
+    return (int(cfg["input_bits"]) + 31) // 32
+
+
+def overlap(cfg: dict, idx: np.ndarray, perm: np.ndarray, frame: np.ndarray) -> np.ndarray:
+    """Algorithm 1 for one packed frame; returns int32[C]."""
+    idx = np.ascontiguousarray(idx, dtype=np.uint32)
+    perm = np.ascontiguousarray(perm, dtype=np.float64)
+    frame = np.ascontiguousarray(frame, dtype=np.uint32).reshape(-1)
+    assert frame.size == _words(cfg)
+    out = np.zeros(int(cfg["num_columns"]), dtype=np.int32)
+    c = _cfg(cfg)
+    _load().spo_overlap(ctypes.byref(c), _ptr(idx), _ptr(perm), _ptr(frame), _ptr(out))
+    return out
+
+
+def inhibit(cfg: dict, ov: np.ndarray):
+    """Algorithm 2 (global form); returns (winners int32[k] -1 padded, active uint8[C])."""
+    ov = np.ascontiguousarray(ov, dtype=np.int32)
+    assert ov.size == int(cfg["num_columns"])
+    active = np.zeros(int(cfg["num_columns"]), dtype=np.uint8)
+    win = np.zeros(int(cfg["winners"]), dtype=np.int32)
+    c = _cfg(cfg)
+    _load().spo_inhibit(ctypes.byref(c), _ptr(ov), _ptr(active), _ptr(win))
+    return win, active
+
+
+def learn(cfg: dict, idx: np.ndarray, perm: np.ndarray, frame: np.ndarray,
+          active: np.ndarray) -> np.ndarray:
+    """Learning on the active columns; returns the updated float64 permanences."""
+    idx = np.ascontiguousarray(idx, dtype=np.uint32)
+    perm = np.array(perm, dtype=np.float64, order="C", copy=True)
+    frame = np.ascontiguousarray(frame, dtype=np.uint32).reshape(-1)
+    active = np.ascontiguousarray(active, dtype=np.uint8)
+    c = _cfg(cfg)
+    _load().spo_learn(ctypes.byref(c), _ptr(idx), _ptr(perm), _ptr(frame), _ptr(active))
+    return perm
+
+
+def run(cfg: dict, idx: np.ndarray, perm: np.ndarray, frames: np.ndarray, learn: bool = True,
+        want_overlaps: bool = True):
+    """F frames in order.  perm may be float32 or float64 on the 1/256 grid.
+
+    Returns (overlaps int32[F][C] or None, winners int32[F][k], perm float64[C][S]).
+    """
+    idx = np.ascontiguousarray(idx, dtype=np.uint32)
+    perm = np.array(perm, dtype=np.float64, order="C", copy=True)
+    frames = np.ascontiguousarray(frames, dtype=np.uint32)
+    F = frames.shape[0] if frames.ndim == 2 else (0 if frames.size == 0 else 1)
+    frames = frames.reshape(F, _words(cfg)) if F else frames.reshape(0, _words(cfg))
+    C, k = int(cfg["num_columns"]), int(cfg["winners"])
+    ov = np.zeros((F, C), dtype=np.int32) if want_overlaps else None
+    win = np.zeros((F, k), dtype=np.int32)
+    c = _cfg(cfg)
+    rc = _load().spo_run(ctypes.byref(c), _ptr(idx), _ptr(perm), _ptr(frames), F, int(bool(learn)),
+                         _ptr(ov) if ov is not None else None, _ptr(win))
+    if rc != 0:
+        raise ValueError("oracle rejected its arguments")
+    return ov, win, perm

@@ -1,0 +1,123 @@
+/*
+ * Oracle for the HTM spatial pooler step -- TEST INFRASTRUCTURE ONLY.
+ * See sp_oracle.h for the paper passages followed and the readings R1-R6.
+ * Each function below is the definition written out, with no blocking,
+ * fusion or reordering beyond the paper's own order of steps.
+ */
+#include "sp_oracle.h"
+
+#include <stdlib.h>
+#include <string.h>
+
+/* R6: input pixel p of a frame is bit (p & 31) of word (p >> 5). */
+static int input_active(const uint32_t* frame, uint32_t p) {
+  return (int)((frame[p >> 5] >> (p & 31u)) & 1u);
+}
+
+/* R1: the synapse is connected when its permanence reaches the threshold. */
+static int synapse_connected(const spo_config* cfg, double perm) {
+  return perm >= cfg->connected_perm;
+}
+
+/* Section 1.1, Algorithm 1: for every column, count its connected synapses
+ * whose input is active; a count below min_overlap becomes 0 (R2), any other
+ * count is multiplied by the column's boost, which is 1 here (R3). */
+void spo_overlap(const spo_config* cfg, const uint32_t* idx, const double* perm,
+                 const uint32_t* frame, int32_t* overlap) {
+  const uint32_t C = cfg->num_columns, S = cfg->synapses_per_column;
+  for (uint32_t c = 0; c < C; ++c) {
+    int32_t ov = 0;
+    for (uint32_t s = 0; s < S; ++s) {
+      const size_t syn = (size_t)c * S + s;
+      if (synapse_connected(cfg, perm[syn])) ov += input_active(frame, idx[syn]);
+    }
+    if (ov < (int32_t)cfg->min_overlap) {
+      ov = 0;
+    } else {
+      const int32_t boost = 1;
+      ov = ov * boost;
+    }
+    overlap[c] = ov;
+  }
+}
+
+/* Section 1.1, Algorithm 2, global form (R4): winners_set_size rounds, each
+ * taking the not-yet-active column of highest overlap; scanning columns in
+ * index order with a strict comparison gives ties to the lower index.  A
+ * round that finds no column with positive overlap ends the selection. */
+int spo_inhibit(const spo_config* cfg, const int32_t* overlap, uint8_t* active,
+                int32_t* winners) {
+  const uint32_t C = cfg->num_columns, k = cfg->winners;
+  memset(active, 0, C);
+  int count = 0;
+  for (uint32_t round = 0; round < k; ++round) {
+    int32_t best = -1;
+    int32_t best_ov = 0;
+    for (uint32_t c = 0; c < C; ++c) {
+      if (!active[c] && overlap[c] > best_ov) {
+        best = (int32_t)c;
+        best_ov = overlap[c];
+      }
+    }
+    if (best < 0) break;
+    active[best] = 1;
+    ++count;
+  }
+  uint32_t w = 0;
+  for (uint32_t c = 0; c < C; ++c)
+    if (active[c]) winners[w++] = (int32_t)c;
+  for (; w < k; ++w) winners[w] = -1;
+  return count;
+}
+
+/* Learning (R5), the whitepaper's spatial pooler phase 3: for each active
+ * column, each potential synapse is strengthened if its input bit is on and
+ * weakened otherwise, the permanence staying within [0, 1]. */
+void spo_learn(const spo_config* cfg, const uint32_t* idx, double* perm,
+               const uint32_t* frame, const uint8_t* active) {
+  const uint32_t C = cfg->num_columns, S = cfg->synapses_per_column;
+  for (uint32_t c = 0; c < C; ++c) {
+    if (!active[c]) continue;
+    for (uint32_t s = 0; s < S; ++s) {
+      const size_t syn = (size_t)c * S + s;
+      double p = perm[syn];
+      if (input_active(frame, idx[syn])) {
+        p = p + cfg->perm_inc;
+        if (p > 1.0) p = 1.0;
+      } else {
+        p = p - cfg->perm_dec;
+        if (p < 0.0) p = 0.0;
+      }
+      perm[syn] = p;
+    }
+  }
+}
+
+int spo_run(const spo_config* cfg, const uint32_t* idx, double* perm,
+            const uint32_t* frames, uint32_t num_frames, int learn,
+            int32_t* overlaps, int32_t* winners) {
+  if (!cfg || !idx || !perm || (!frames && num_frames) || (!winners && num_frames)) return -1;
+  const uint32_t C = cfg->num_columns, k = cfg->winners;
+  if (C == 0 || cfg->synapses_per_column == 0 || k == 0 || k > C || cfg->input_bits == 0)
+    return -1;
+  const size_t W = ((size_t)cfg->input_bits + 31) / 32;
+  for (size_t i = 0; i < (size_t)C * cfg->synapses_per_column; ++i)
+    if (idx[i] >= cfg->input_bits) return -1;
+  int32_t* ov = (int32_t*)malloc(sizeof(int32_t) * C);
+  uint8_t* active = (uint8_t*)malloc(C);
+  if (!ov || !active) {
+    free(ov);
+    free(active);
+    return -1;
+  }
+  for (uint32_t t = 0; t < num_frames; ++t) {
+    const uint32_t* frame = frames + (size_t)t * W;
+    spo_overlap(cfg, idx, perm, frame, ov);
+    spo_inhibit(cfg, ov, active, winners + (size_t)t * k);
+    if (learn) spo_learn(cfg, idx, perm, frame, active);
+    if (overlaps) memcpy(overlaps + (size_t)t * C, ov, sizeof(int32_t) * C);
+  }
+  free(ov);
+  free(active);
+  return 0;
+}

@@ -1,0 +1,155 @@
+"""Seeded synthetic inputs for the spatial pooler: frames, potential pools and
+initial permanences.
+
+This module holds none of the spatial pooler's arithmetic (no overlap, no
+inhibition, no learning); it only draws random inputs and packs bits, so that
+both the GPU library's tests and the oracle's tests can be fed the same data.
+
+The paper's video dataset (rendered "shapes" clips binarised by an adaptive
+threshold, Section 4.2 and Section 3.1.2) is not available, so seeded frames
+stand in for it: Bernoulli pixels, or random 8x8 blobs that mimic the
+clustered foreground an adaptive threshold leaves.
+
+Bit layout: pixel p = y * width + x of a frame is bit (p & 31) of 32-bit word
+(p >> 5), least significant bit first; bits past the frame's last pixel are 0.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+GRID = 256  # permanences live on the 1/256 grid
+
+
+def rng(seed: int, stream: int = 0) -> np.random.Generator:
+    """Independent generator ``stream`` of ``seed``."""
+    return np.random.default_rng(np.random.SeedSequence(seed).spawn(stream + 1)[stream])
+
+
+def words_per_frame(input_bits: int) -> int:
+    return (int(input_bits) + 31) // 32
+
+
+def pack_bits(bits: np.ndarray) -> np.ndarray:
+    """bool[..., N] -> uint32[..., ceil(N/32)], LSB-first."""
+    bits = np.asarray(bits, dtype=bool)
+    n = bits.shape[-1]
+    w = words_per_frame(n)
+    pad = w * 32 - n
+    if pad:
+        bits = np.concatenate([bits, np.zeros(bits.shape[:-1] + (pad,), dtype=bool)], axis=-1)
+    by = np.packbits(bits, axis=-1, bitorder="little")
+    return np.ascontiguousarray(by).view("<u4").astype(np.uint32, copy=False)
+
+
+def unpack_bits(words: np.ndarray, n: int) -> np.ndarray:
+    """uint32[..., W] -> bool[..., n]."""
+    words = np.ascontiguousarray(words, dtype="<u4")
+    by = words.view(np.uint8)
+    return np.unpackbits(by, axis=-1, bitorder="little")[..., :n].astype(bool)
+
+
+def pools(g: np.random.Generator, input_bits: int, columns: int, synapses: int) -> np.ndarray:
+    """Potential pools: per column, ``synapses`` distinct inputs drawn uniformly
+    without replacement, sorted ascending.  uint32[C][S]."""
+    out = np.empty((columns, synapses), dtype=np.uint32)
+    for c in range(columns):
+        out[c] = np.sort(g.choice(input_bits, size=synapses, replace=False))
+    return out
+
+
+def permanences_q(g: np.random.Generator, columns: int, synapses: int) -> np.ndarray:
+    """Initial permanences in 1/256 units, uniform over {0, ..., 256}.  uint16[C][S]."""
+    return g.integers(0, GRID + 1, size=(columns, synapses), dtype=np.uint16)
+
+
+def q_to_float(q: np.ndarray) -> np.ndarray:
+    return (np.asarray(q, dtype=np.float32) / np.float32(GRID)).astype(np.float32)
+
+
+def bernoulli_frames(g: np.random.Generator, frames: int, input_bits: int, p: float) -> np.ndarray:
+    """uint32[F][W]: every pixel on with probability p, independently."""
+    out = np.empty((frames, words_per_frame(input_bits)), dtype=np.uint32)
+    for t in range(frames):
+        out[t] = pack_bits(g.random(input_bits) < p)
+    return out
+
+
+def blob_frames(g: np.random.Generator, frames: int, width: int, height: int,
+                density: float = 0.05, blob: int = 8) -> np.ndarray:
+    """uint32[F][W]: blob x blob squares at uniform top-left corners, added
+    until at least ``density`` of the width x height pixels are on."""
+    n = width * height
+    target = int(np.ceil(density * n))
+    out = np.empty((frames, words_per_frame(n)), dtype=np.uint32)
+    for t in range(frames):
+        img = np.zeros((height, width), dtype=bool)
+        on = 0
+        while on < target:
+            ys = g.integers(0, height - blob + 1, size=32)
+            xs = g.integers(0, width - blob + 1, size=32)
+            for y, x in zip(ys, xs):
+                img[y:y + blob, x:x + blob] = True
+            on = int(img.sum())
+        out[t] = pack_bits(img.reshape(-1))
+    return out
+
+
+@dataclass
+class Workload:
+    """One spatial pooler instance plus its input frames."""
+    name: str
+    cfg: dict
+    idx: np.ndarray                 # uint32[C][S]
+    perm_q: np.ndarray              # uint16[C][S] (1/256 units)
+    frames: np.ndarray              # uint32[F][W]
+    learn: bool = True
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def perm(self) -> np.ndarray:
+        return q_to_float(self.perm_q)
+
+
+def sp_config(input_bits, columns, synapses, min_overlap, winners,
+              connected_q8=128, inc_q8=8, dec_q8=4) -> dict:
+    return dict(input_bits=int(input_bits), num_columns=int(columns),
+                synapses_per_column=int(synapses), min_overlap=int(min_overlap),
+                winners=int(winners), connected_q8=int(connected_q8),
+                inc_q8=int(inc_q8), dec_q8=int(dec_q8))
+
+
+def random_instance(seed: int, cfg: dict, frames: int, density: float = 0.1,
+                    shape: tuple | None = None, blobs: bool = False) -> Workload:
+    """Pools, permanences and frames for ``cfg`` from ``seed`` (three
+    independent generator streams)."""
+    n, C, S = cfg["input_bits"], cfg["num_columns"], cfg["synapses_per_column"]
+    idx = pools(rng(seed, 0), n, C, S)
+    q = permanences_q(rng(seed, 1), C, S)
+    if blobs:
+        w, h = shape
+        fr = blob_frames(rng(seed, 2), frames, w, h, density)
+    else:
+        fr = bernoulli_frames(rng(seed, 2), frames, n, density)
+    return Workload(name=f"random_{seed}", cfg=cfg, idx=idx, perm_q=q, frames=fr)
+
+
+def workload_plain_32x32(frames: int = 100) -> Workload:
+    """32x32 input, Bernoulli(0.10) pixels; 256 columns x 64 synapses;
+    min_overlap 4, 20 winners, threshold 0.5, inc 8/256, dec 4/256; learning on."""
+    cfg = sp_config(32 * 32, 256, 64, 4, 20)
+    w = random_instance(1, cfg, frames, density=0.10)
+    w.name = "plain_32x32_256c_64s"
+    return w
+
+
+def workload_paper_scale(frames: int = 1000, columns: int = 1024, synapses: int = 256,
+                         seed: int = 2) -> Workload:
+    """960x540 input, ~5% on as random 8x8 blobs; 1024 columns x 256 synapses
+    (sweepable); min_overlap 4, 40 winners, threshold 0.5, inc 8/256,
+    dec 4/256; learning on."""
+    cfg = sp_config(960 * 540, columns, synapses, 4, 40)
+    w = random_instance(seed, cfg, frames, density=0.05, shape=(960, 540), blobs=True)
+    w.name = f"paper_960x540_{columns}c_{synapses}s"
+    return w

@@ -1,0 +1,150 @@
+/*
+ * htmsp -- HTM spatial pooler step on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the library libhtmsp.so.  One spatial pooler instance maps a
+ * binary input frame to a sparse set of winning columns and, when learning,
+ * updates its synapse permanences (Wielgosz & Pietron, arXiv 1608.01966,
+ * Section 1.1):
+ *
+ *   overlap     Algorithm 1: per column, the number of connected synapses
+ *               (permanence >= connected threshold) whose input bit is on;
+ *               a count below min_overlap becomes 0; boost is 1.
+ *   inhibition  Algorithm 2, global form: the winners_set_size columns of
+ *               highest positive overlap, ties to the lower column index;
+ *               a column with overlap 0 never wins, so fewer than
+ *               winners_set_size columns win when fewer have overlap > 0.
+ *   learning    the learning stage the paper takes from the Numenta CLA
+ *               whitepaper: for every winner, each potential synapse gains
+ *               inc if its input bit is on and loses dec otherwise, clipped
+ *               to [0, 1].
+ *
+ * Data layout (all device memory, row-major, no padding):
+ *   idx     uint32 [C][S]  input pixel of each potential synapse, < N
+ *   perm    float  [C][S]  permanence, a multiple of 1/256 in [0, 1]
+ *   frames  uint32 [F][W]  W = ceil(N / 32); pixel p is bit (p & 31) of word
+ *                          (p >> 5), least significant bit first; bits at or
+ *                          past N are ignored
+ *   overlaps int32 [F][C]  gated overlap per frame and column
+ *   winners  int32 [F][k]  winners of each frame in ascending column order,
+ *                          padded with -1
+ *
+ * Permanences are restricted to the 1/256 grid (and inc, dec and the
+ * threshold are given in 1/256 units) so that every update is exact in FP32
+ * and results are reproducible bit for bit.
+ *
+ * Ownership: idx and perm are caller-owned device buffers that the handle
+ * borrows for its lifetime; the library reads idx and reads/writes perm in
+ * place.  frames, overlaps and winners are caller-owned per call.  The
+ * library allocates only a small per-handle workspace (sp_workspace_bytes)
+ * in sp_create and frees it in sp_destroy.
+ *
+ * Streams: `stream` is a hipStream_t (NULL = the null stream).  Steps are
+ * enqueued and return at once; results are valid once the stream has
+ * synchronised.  A handle must not be used by two calls at the same time.
+ *
+ * Errors: every call returns SP_OK (0) or a negative sp_status; argument and
+ * configuration checks happen on the host before anything is enqueued, and
+ * out-parameters are written only on SP_OK.  sp_last_error() describes the
+ * last failure of the calling thread.  Nothing is thrown across the ABI.
+ */
+#ifndef HTMSP_SP_H
+#define HTMSP_SP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum sp_status {
+  SP_OK = 0,
+  SP_EINVAL = -1,  /* bad argument, configuration or state contents        */
+  SP_ENOMEM = -2,  /* workspace allocation failed                          */
+  SP_EDEVICE = -3, /* HIP error, no usable device, or a failed device step */
+  SP_EBROKEN = -4  /* the handle saw a device failure and must be destroyed */
+} sp_status;
+
+/* Limits checked by sp_config_check. */
+#define SP_MAX_INPUT_BITS (1u << 23)
+#define SP_MAX_COLUMNS 65536u
+#define SP_MAX_SYNAPSES 4096u
+
+typedef struct sp_config {
+  uint32_t input_bits;          /* N, 1..SP_MAX_INPUT_BITS                   */
+  uint32_t num_columns;         /* C, 1..SP_MAX_COLUMNS                      */
+  uint32_t synapses_per_column; /* S, 1..SP_MAX_SYNAPSES                     */
+  uint32_t min_overlap;         /* m (any value; m > S means no winners)     */
+  uint32_t winners;             /* k = winners_set_size, 1..C                */
+  uint32_t connected_q8;        /* connected threshold x 256, 0..256         */
+  uint32_t inc_q8;              /* permanence increment x 256, 0..256        */
+  uint32_t dec_q8;              /* permanence decrement x 256, 0..256        */
+} sp_config;
+
+typedef struct sp_handle sp_handle;
+
+/* Host-only check of a configuration against the limits above. */
+int sp_config_check(const sp_config* cfg);
+
+/* Words per packed frame, ceil(N / 32); 0 for an invalid configuration. */
+size_t sp_frame_words(const sp_config* cfg);
+
+/* Bytes of device workspace sp_create allocates for this configuration; 0
+ * for an invalid configuration. */
+size_t sp_workspace_bytes(const sp_config* cfg);
+
+/* Host-only check of state held in host memory: every idx < N and every
+ * permanence a multiple of 1/256 in [0, 1].  SP_EINVAL names the first bad
+ * entry. */
+int sp_check_state_host(const sp_config* cfg, const uint32_t* idx, const float* perm);
+
+/* Creates a handle over the caller's device state (borrowed, see above) on
+ * the current HIP device.  Validates the configuration on the host and the
+ * state contents on the device (synchronising `stream`): SP_EINVAL if an
+ * index is >= N or a permanence is off the 1/256 grid. */
+int sp_create(const sp_config* cfg, uint32_t* idx_dev, float* perm_dev, void* stream,
+              sp_handle** out);
+
+/* Re-validates the borrowed state on the device after the caller changed it
+ * (synchronises `stream`). */
+int sp_check_state(sp_handle* h, void* stream);
+
+/* One spatial pooler step for each of F frames, in order (Section 1.1:
+ * overlap, inhibition, then learning when learn != 0, the permanences left
+ * by frame t feeding frame t + 1).  learn == 0 leaves the state untouched.
+ * overlaps may be NULL; winners must not be.  F == 0 is a no-op.
+ *
+ * The frames run in one persistent launch that keeps the handle's synapse
+ * state on chip (one workgroup per group of columns, the per-frame overlaps
+ * exchanged through device memory); shapes it cannot hold run as
+ * sp_step_plain.  A device-side failure of the persistent launch is reported
+ * by the next sp_sync. */
+int sp_step(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames, int learn,
+            int32_t* overlaps_dev, int32_t* winners_dev, void* stream);
+
+/* Same contract as sp_step, executed one frame per launch sequence
+ * (overlap, inhibition, learning kernels per frame): the plain baseline. */
+int sp_step_plain(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames, int learn,
+                  int32_t* overlaps_dev, int32_t* winners_dev, void* stream);
+
+/* 1 if sp_step runs this handle's shape as one persistent launch, 0 if it
+ * runs the plain path, negative on a bad handle. */
+int sp_step_is_persistent(const sp_handle* h);
+
+/* Synchronises `stream` and reports a device-side failure of an earlier
+ * step on this handle (SP_EDEVICE, after which the handle is SP_EBROKEN). */
+int sp_sync(sp_handle* h, void* stream);
+
+/* Frees the workspace (synchronising the device first).  NULL is accepted.
+ * The borrowed state is left as it is. */
+int sp_destroy(sp_handle* h);
+
+/* Message for the calling thread's last failure ("" if none).  Valid until
+ * the thread's next call into the library. */
+const char* sp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

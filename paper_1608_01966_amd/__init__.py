@@ -1,0 +1,203 @@
+"""htmsp -- the HTM spatial pooler step (Wielgosz & Pietron, arXiv 1608.01966,
+Section 1.1) on AMD Instinct MI355X.
+
+Thin Python binding over the C ABI of ``libhtmsp.so`` (``include/sp.h``):
+each ``sp_*`` function here has the C function's name and only marshals
+arguments (torch device tensors -> device pointers, torch streams -> HIP
+streams).  Every step of the computation runs in the library's HIP kernels.
+
+Tensor conventions (all on the GPU, contiguous):
+  idx     int32  [C][S]  input pixel per potential synapse (uint32 bits)
+  perm    float32[C][S]  permanences on the 1/256 grid
+  frames  int32  [F][W]  packed frames, W = ceil(N/32) (uint32 bits)
+  overlaps int32 [F][C]
+  winners  int32 [F][k]  ascending, -1 padded
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import synth
+from ._native import (SP_EBROKEN, SP_EDEVICE, SP_EINVAL, SP_ENOMEM, SP_OK, SpConfig, lib)
+
+__all__ = [
+    "SpError", "SpatialPooler", "synth", "sp_config_check", "sp_frame_words",
+    "sp_workspace_bytes", "sp_check_state_host", "sp_create", "sp_check_state", "sp_step",
+    "sp_step_plain", "sp_step_is_persistent", "sp_sync", "sp_destroy", "sp_last_error",
+    "SP_OK", "SP_EINVAL", "SP_ENOMEM", "SP_EDEVICE", "SP_EBROKEN",
+]
+
+
+class SpError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+def sp_last_error() -> str:
+    return lib().sp_last_error().decode()
+
+
+def _check(rc: int, what: str) -> int:
+    if rc < 0:
+        raise SpError(rc, f"{what}: {sp_last_error()}")
+    return rc
+
+
+def _cfg(cfg) -> SpConfig:
+    return cfg if isinstance(cfg, SpConfig) else SpConfig.from_dict(cfg)
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _dev(t, dtype, shape, name):
+    """Device pointer of a contiguous CUDA tensor of the given dtype/shape."""
+    import torch
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def sp_config_check(cfg) -> None:
+    c = _cfg(cfg)
+    _check(lib().sp_config_check(ctypes.byref(c)), "sp_config_check")
+
+
+def sp_frame_words(cfg) -> int:
+    c = _cfg(cfg)
+    return int(lib().sp_frame_words(ctypes.byref(c)))
+
+
+def sp_workspace_bytes(cfg) -> int:
+    c = _cfg(cfg)
+    return int(lib().sp_workspace_bytes(ctypes.byref(c)))
+
+
+def sp_check_state_host(cfg, idx: np.ndarray, perm: np.ndarray) -> None:
+    c = _cfg(cfg)
+    n = c.num_columns * c.synapses_per_column
+    idx = np.ascontiguousarray(idx, dtype=np.uint32)
+    perm = np.ascontiguousarray(perm, dtype=np.float32)
+    if idx.size != n or perm.size != n:
+        raise ValueError("idx and perm must hold num_columns * synapses_per_column entries")
+    _check(lib().sp_check_state_host(ctypes.byref(c), idx.ctypes.data_as(ctypes.c_void_p),
+                                     perm.ctypes.data_as(ctypes.c_void_p)), "sp_check_state_host")
+
+
+def sp_create(cfg, idx, perm, stream=None) -> int:
+    """Returns an opaque handle (int).  idx and perm are borrowed: keep them
+    alive until sp_destroy."""
+    import torch
+    c = _cfg(cfg)
+    shape = (c.num_columns, c.synapses_per_column)
+    pi = _dev(idx, torch.int32, shape, "idx")
+    pp = _dev(perm, torch.float32, shape, "perm")
+    out = ctypes.c_void_p()
+    _check(lib().sp_create(ctypes.byref(c), pi, pp, _stream(stream), ctypes.byref(out)),
+           "sp_create")
+    return int(out.value)
+
+
+def sp_check_state(h: int, stream=None) -> None:
+    _check(lib().sp_check_state(ctypes.c_void_p(h), _stream(stream)), "sp_check_state")
+
+
+def _step(fn, name, h, cfg, frames, learn, overlaps, winners, stream):
+    import torch
+    c = _cfg(cfg)
+    F = int(frames.shape[0]) if frames is not None else 0
+    W = (c.input_bits + 31) // 32
+    pf = _dev(frames, torch.int32, (F, W), "frames")
+    po = _dev(overlaps, torch.int32, (F, c.num_columns), "overlaps")
+    pw = _dev(winners, torch.int32, (F, c.winners), "winners")
+    _check(fn(ctypes.c_void_p(h), pf, F, int(bool(learn)), po, pw, _stream(stream)), name)
+
+
+def sp_step(h: int, cfg, frames, learn: bool, overlaps, winners, stream=None) -> None:
+    _step(lib().sp_step, "sp_step", h, cfg, frames, learn, overlaps, winners, stream)
+
+
+def sp_step_plain(h: int, cfg, frames, learn: bool, overlaps, winners, stream=None) -> None:
+    _step(lib().sp_step_plain, "sp_step_plain", h, cfg, frames, learn, overlaps, winners, stream)
+
+
+def sp_step_is_persistent(h: int) -> bool:
+    return bool(_check(lib().sp_step_is_persistent(ctypes.c_void_p(h)), "sp_step_is_persistent"))
+
+
+def sp_sync(h: int, stream=None) -> None:
+    _check(lib().sp_sync(ctypes.c_void_p(h), _stream(stream)), "sp_sync")
+
+
+def sp_destroy(h: int) -> None:
+    _check(lib().sp_destroy(ctypes.c_void_p(h) if h else None), "sp_destroy")
+
+
+class SpatialPooler:
+    """One spatial pooler instance whose state lives in GPU memory.
+
+    ``cfg`` is a dict with the fields of ``sp_config``; ``idx`` (uint32 or
+    int32 [C][S]) and ``perm`` (float32 [C][S], 1/256 grid) may be numpy
+    arrays or GPU tensors; they are copied to GPU tensors owned by the
+    instance."""
+
+    def __init__(self, cfg: dict, idx, perm, device="cuda", stream=None):
+        import torch
+        self.cfg = dict(cfg)
+        if isinstance(idx, np.ndarray):
+            idx = torch.from_numpy(np.ascontiguousarray(idx).astype(np.uint32).view(np.int32))
+        if isinstance(perm, np.ndarray):
+            perm = torch.from_numpy(np.ascontiguousarray(perm, dtype=np.float32))
+        self.idx = idx.to(device=device, dtype=torch.int32).contiguous()
+        self.perm = perm.to(device=device, dtype=torch.float32).contiguous()
+        self.handle = sp_create(self.cfg, self.idx, self.perm, stream)
+
+    @property
+    def persistent(self) -> bool:
+        return sp_step_is_persistent(self.handle)
+
+    def step(self, frames, learn: bool = True, overlaps: bool = True, plain: bool = False,
+             stream=None):
+        """frames: int32 GPU tensor [F][W] (or uint32 numpy).  Returns
+        (overlaps [F][C] or None, winners [F][k]) GPU tensors, valid after the
+        stream synchronises."""
+        import torch
+        if isinstance(frames, np.ndarray):
+            frames = torch.from_numpy(np.ascontiguousarray(frames, dtype=np.uint32).view(np.int32))
+        frames = frames.to(device=self.idx.device).contiguous()
+        F = frames.shape[0]
+        ov = torch.empty((F, self.cfg["num_columns"]), dtype=torch.int32,
+                         device=self.idx.device) if overlaps else None
+        win = torch.empty((F, self.cfg["winners"]), dtype=torch.int32, device=self.idx.device)
+        fn = sp_step_plain if plain else sp_step
+        fn(self.handle, self.cfg, frames, learn, ov, win, stream)
+        return ov, win
+
+    def sync(self, stream=None) -> None:
+        sp_sync(self.handle, stream)
+
+    def close(self) -> None:
+        if self.handle:
+            sp_destroy(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

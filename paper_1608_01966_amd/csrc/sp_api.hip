@@ -1,0 +1,375 @@
+// Host side of the C ABI declared in include/sp.h: argument checks, the
+// per-handle workspace, the choice between the persistent and the plain
+// execution, and kernel launches.  No exception crosses the ABI; every entry
+// point returns an sp_status and records a message for sp_last_error().
+#include <stdarg.h>
+#include <stdio.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+
+#include "sp.h"
+#include "sp_internal.h"
+
+using htmsp::Shape;
+
+struct sp_handle {
+  sp_config cfg;
+  Shape sh;
+  uint32_t* idx;  // borrowed [C][S]
+  float* perm;    // borrowed [C][S]
+  int device;
+  void* ws;
+  size_t ws_bytes;
+  uint32_t* xchg;      // [2][C]
+  uint32_t* err;       // [1] (padded)
+  uint32_t* check;     // [4]
+  int32_t* ov_scratch; // [C]
+  uint64_t xchg_frames;
+  bool persistent;
+  uint32_t cpw, rpc, grid, rows;
+  const void* pkernel;
+  size_t plds;
+  bool broken;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int ok() {
+  g_err.clear();
+  return SP_OK;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(SP_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Workspace layout, each part 256-byte aligned.
+struct WsLayout {
+  size_t xchg, err, check, ov, total;
+};
+
+WsLayout ws_layout(const sp_config& c) {
+  WsLayout l;
+  l.xchg = 0;
+  l.err = align_up(l.xchg + sizeof(uint32_t) * 2 * (size_t)c.num_columns, 256);
+  l.check = align_up(l.err + sizeof(uint32_t), 256);
+  l.ov = align_up(l.check + 4 * sizeof(uint32_t), 256);
+  l.total = align_up(l.ov + sizeof(int32_t) * (size_t)c.num_columns, 256);
+  return l;
+}
+
+int check_config(const sp_config* c) {
+  if (!c) return fail(SP_EINVAL, "config is NULL");
+  if (c->input_bits < 1 || c->input_bits > SP_MAX_INPUT_BITS)
+    return fail(SP_EINVAL, "input_bits=%u outside 1..%u", c->input_bits, SP_MAX_INPUT_BITS);
+  if (c->num_columns < 1 || c->num_columns > SP_MAX_COLUMNS)
+    return fail(SP_EINVAL, "num_columns=%u outside 1..%u", c->num_columns, SP_MAX_COLUMNS);
+  if (c->synapses_per_column < 1 || c->synapses_per_column > SP_MAX_SYNAPSES)
+    return fail(SP_EINVAL, "synapses_per_column=%u outside 1..%u", c->synapses_per_column,
+                SP_MAX_SYNAPSES);
+  if (c->winners < 1 || c->winners > c->num_columns)
+    return fail(SP_EINVAL, "winners=%u outside 1..num_columns=%u", c->winners, c->num_columns);
+  if (c->connected_q8 > 256) return fail(SP_EINVAL, "connected_q8=%u > 256", c->connected_q8);
+  if (c->inc_q8 > 256) return fail(SP_EINVAL, "inc_q8=%u > 256", c->inc_q8);
+  if (c->dec_q8 > 256) return fail(SP_EINVAL, "dec_q8=%u > 256", c->dec_q8);
+  return SP_OK;
+}
+
+Shape make_shape(const sp_config& c) {
+  Shape s;
+  s.N = c.input_bits;
+  s.C = c.num_columns;
+  s.S = c.synapses_per_column;
+  s.W = (c.input_bits + 31) / 32;
+  s.m = c.min_overlap;
+  s.k = c.winners;
+  s.theta = c.connected_q8;
+  s.inc = c.inc_q8;
+  s.dec = c.dec_q8;
+  return s;
+}
+
+bool aligned4(const void* p) { return ((uintptr_t)p & 3u) == 0; }
+
+// Makes the handle's device current for the scope of a call.
+struct DeviceScope {
+  int prev = -1;
+  explicit DeviceScope(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) {
+      if (hipSetDevice(dev) != hipSuccess) prev = -1;
+    } else {
+      prev = -1;
+    }
+  }
+  ~DeviceScope() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+int check_handle(const sp_handle* h) {
+  if (!h) return fail(SP_EINVAL, "handle is NULL");
+  if (h->broken) return fail(SP_EBROKEN, "handle saw a device failure; destroy it");
+  return SP_OK;
+}
+
+int check_step_args(const sp_handle* h, const uint32_t* frames, uint32_t F, int32_t* ov,
+                    int32_t* win) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (F == 0) return SP_OK;
+  if (!frames) return fail(SP_EINVAL, "frames is NULL with num_frames=%u", F);
+  if (!win) return fail(SP_EINVAL, "winners is NULL");
+  if (!aligned4(frames) || !aligned4(win) || (ov && !aligned4(ov)))
+    return fail(SP_EINVAL, "frames, overlaps and winners must be 4-byte aligned");
+  return SP_OK;
+}
+
+// Spin polls one workgroup makes for one frame before it gives up (several
+// seconds; a correct launch needs a tiny fraction of it).
+constexpr uint32_t kSpinLimit = 1u << 21;
+
+void plan_persistent(sp_handle* h) {
+  h->persistent = false;
+  int dev = h->device, cus = 0, coop = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return;
+  if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess) return;
+  const Shape& sh = h->sh;
+  if (!coop || cus <= 0 || sh.C > htmsp::kPersistMaxColumns) return;
+  const uint32_t rpc = (sh.S + 63) / 64;
+  uint32_t cpw = (sh.C + (uint32_t)cus - 1) / (uint32_t)cus;
+  if (cpw * rpc > (uint32_t)htmsp::kPersistMaxRows) cpw = (uint32_t)htmsp::kPersistMaxRows / rpc;
+  if (cpw == 0) return;
+  const uint32_t grid = (sh.C + cpw - 1) / cpw;
+  const uint32_t rows = cpw * rpc;
+  const void* k = htmsp::persistent_kernel(rows);
+  if (!k) return;
+  const size_t lds = htmsp::persistent_lds_bytes(sh);
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 64, lds) != hipSuccess) return;
+  if ((uint64_t)per_cu * (uint64_t)cus < grid) return;
+  h->cpw = cpw;
+  h->rpc = rpc;
+  h->grid = grid;
+  h->rows = rows;
+  h->pkernel = k;
+  h->plds = lds;
+  h->persistent = true;
+}
+
+int run_check_state(sp_handle* h, hipStream_t s) {
+  const size_t n = (size_t)h->sh.C * h->sh.S;
+  hipError_t e = htmsp::launch_check_state(h->idx, h->perm, n, h->sh.N, h->check, s);
+  if (e != hipSuccess) return hip_fail(e, "state check launch");
+  uint32_t out[4];
+  e = hipMemcpyAsync(out, h->check, sizeof(out), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "state check");
+  if (out[0])
+    return fail(SP_EINVAL, "%u synapse indices >= input_bits=%u (first at flat position %u)",
+                out[0], h->sh.N, out[2]);
+  if (out[1])
+    return fail(SP_EINVAL,
+                "%u permanences off the 1/256 grid or outside [0,1] (first at flat position %u)",
+                out[1], out[3]);
+  return SP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sp_config_check(const sp_config* cfg) {
+  int rc = check_config(cfg);
+  return rc ? rc : ok();
+}
+
+size_t sp_frame_words(const sp_config* cfg) {
+  if (check_config(cfg)) return 0;
+  return ((size_t)cfg->input_bits + 31) / 32;
+}
+
+size_t sp_workspace_bytes(const sp_config* cfg) {
+  if (check_config(cfg)) return 0;
+  return ws_layout(*cfg).total;
+}
+
+int sp_check_state_host(const sp_config* cfg, const uint32_t* idx, const float* perm) {
+  int rc = check_config(cfg);
+  if (rc) return rc;
+  if (!idx || !perm) return fail(SP_EINVAL, "idx or perm is NULL");
+  const size_t n = (size_t)cfg->num_columns * cfg->synapses_per_column;
+  for (size_t i = 0; i < n; ++i) {
+    if (idx[i] >= cfg->input_bits)
+      return fail(SP_EINVAL, "idx[%zu]=%u >= input_bits=%u", i, idx[i], cfg->input_bits);
+    const float q = perm[i] * 256.0f;
+    if (!(q >= 0.0f && q <= 256.0f && q == (float)(int)q))
+      return fail(SP_EINVAL, "perm[%zu]=%.9g is off the 1/256 grid or outside [0,1]", i,
+                  (double)perm[i]);
+  }
+  return ok();
+}
+
+int sp_create(const sp_config* cfg, uint32_t* idx_dev, float* perm_dev, void* stream,
+              sp_handle** out) {
+  int rc = check_config(cfg);
+  if (rc) return rc;
+  if (!out) return fail(SP_EINVAL, "out is NULL");
+  if (!idx_dev || !perm_dev) return fail(SP_EINVAL, "idx or perm is NULL");
+  if (!aligned4(idx_dev) || !aligned4(perm_dev))
+    return fail(SP_EINVAL, "idx and perm must be 4-byte aligned");
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+
+  sp_handle* h = new (std::nothrow) sp_handle();
+  if (!h) return fail(SP_ENOMEM, "host allocation failed");
+  h->cfg = *cfg;
+  h->sh = make_shape(*cfg);
+  h->idx = idx_dev;
+  h->perm = perm_dev;
+  h->device = dev;
+  const WsLayout l = ws_layout(*cfg);
+  h->ws_bytes = l.total;
+  e = hipMalloc(&h->ws, l.total);
+  if (e != hipSuccess) {
+    delete h;
+    return fail(SP_ENOMEM, "workspace hipMalloc(%zu): %s", l.total, hipGetErrorString(e));
+  }
+  char* base = static_cast<char*>(h->ws);
+  h->xchg = reinterpret_cast<uint32_t*>(base + l.xchg);
+  h->err = reinterpret_cast<uint32_t*>(base + l.err);
+  h->check = reinterpret_cast<uint32_t*>(base + l.check);
+  h->ov_scratch = reinterpret_cast<int32_t*>(base + l.ov);
+  e = hipMemsetAsync(h->ws, 0, l.total, s);
+  if (e != hipSuccess) {
+    (void)hipFree(h->ws);
+    delete h;
+    return hip_fail(e, "workspace clear");
+  }
+  rc = run_check_state(h, s);
+  if (rc) {
+    (void)hipFree(h->ws);
+    delete h;
+    return rc;
+  }
+  plan_persistent(h);
+  *out = h;
+  return ok();
+}
+
+int sp_check_state(sp_handle* h, void* stream) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  DeviceScope ds(h->device);
+  rc = run_check_state(h, static_cast<hipStream_t>(stream));
+  return rc ? rc : ok();
+}
+
+int sp_step_plain(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames, int learn,
+                  int32_t* overlaps_dev, int32_t* winners_dev, void* stream) {
+  int rc = check_step_args(h, frames_dev, num_frames, overlaps_dev, winners_dev);
+  if (rc) return rc;
+  DeviceScope ds(h->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const Shape& sh = h->sh;
+  for (uint32_t t = 0; t < num_frames; ++t) {
+    const uint32_t* frame = frames_dev + (size_t)t * sh.W;
+    int32_t* ov = overlaps_dev ? overlaps_dev + (size_t)t * sh.C : h->ov_scratch;
+    int32_t* win = winners_dev + (size_t)t * sh.k;
+    hipError_t e = htmsp::launch_overlap_plain(h->idx, h->perm, frame, ov, sh, s);
+    if (e == hipSuccess) e = htmsp::launch_topk_plain(ov, win, sh, s);
+    if (e == hipSuccess && learn) e = htmsp::launch_learn_plain(h->idx, h->perm, frame, win, sh, s);
+    if (e != hipSuccess) return hip_fail(e, "plain step launch");
+  }
+  return ok();
+}
+
+int sp_step(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames, int learn,
+            int32_t* overlaps_dev, int32_t* winners_dev, void* stream) {
+  int rc = check_step_args(h, frames_dev, num_frames, overlaps_dev, winners_dev);
+  if (rc) return rc;
+  if (num_frames == 0) return ok();
+  if (!h->persistent)
+    return sp_step_plain(h, frames_dev, num_frames, learn, overlaps_dev, winners_dev, stream);
+  DeviceScope ds(h->device);
+  htmsp::PersistArgs a;
+  a.idx = h->idx;
+  a.perm = h->perm;
+  a.frames = frames_dev;
+  a.ov_out = overlaps_dev;
+  a.win_out = winners_dev;
+  a.xchg = h->xchg;
+  a.err = h->err;
+  a.F = num_frames;
+  a.learn = learn ? 1u : 0u;
+  a.frame_base = (uint32_t)h->xchg_frames;
+  a.cpw = h->cpw;
+  a.rpc = h->rpc;
+  a.spin_limit = kSpinLimit;
+  a.sh = h->sh;
+  void* args[] = {&a};
+  hipError_t e = hipLaunchCooperativeKernel(h->pkernel, dim3(h->grid), dim3(64), args,
+                                            (unsigned int)h->plds,
+                                            static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "persistent step launch");
+  h->xchg_frames += num_frames;
+  return ok();
+}
+
+int sp_step_is_persistent(const sp_handle* h) {
+  if (!h) return fail(SP_EINVAL, "handle is NULL");
+  return h->persistent ? 1 : 0;
+}
+
+int sp_sync(sp_handle* h, void* stream) {
+  if (!h) return fail(SP_EINVAL, "handle is NULL");
+  DeviceScope ds(h->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  uint32_t err = 0;
+  hipError_t e = hipMemcpyAsync(&err, h->err, sizeof(err), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    h->broken = true;
+    return hip_fail(e, "sync");
+  }
+  if (err) {
+    h->broken = true;
+    return fail(SP_EDEVICE, "a persistent step gave up waiting for the per-frame exchange");
+  }
+  if (h->broken) return fail(SP_EBROKEN, "handle saw a device failure; destroy it");
+  return ok();
+}
+
+int sp_destroy(sp_handle* h) {
+  if (!h) return ok();
+  int rc = SP_OK;
+  {
+    DeviceScope ds(h->device);
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipFree(h->ws);
+    if (e != hipSuccess) rc = hip_fail(e, "destroy");
+  }
+  delete h;
+  return rc ? rc : ok();
+}
+
+const char* sp_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,83 @@
+"""The C ABI without a GPU: the library loads, exports every function that
+include/sp.h declares, and its host-only checks behave as documented."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1608_01966_amd as sp
+from paper_1608_01966_amd import _native, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = set()
+    inc = os.path.join(ROOT, "include")
+    for f in os.listdir(inc):
+        if f.endswith(".h"):
+            text = open(os.path.join(inc, f)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(sp_[a-z_0-9]+)\s*\(", text))
+    return names
+
+
+def test_library_exports_every_declared_function():
+    L = _native.lib()
+    declared = _declared_functions()
+    assert declared, "no declarations found"
+    for name in declared:
+        assert hasattr(L, name), name
+    assert declared == {n for n, _, _ in _native.SIGNATURES}
+
+
+def test_config_checks():
+    good = synth.sp_config(518400, 1024, 256, 4, 40)
+    sp.sp_config_check(good)
+    assert sp.sp_frame_words(good) == 16200
+    assert sp.sp_workspace_bytes(good) >= 4 * 3 * 1024
+    bad = [
+        dict(input_bits=0), dict(input_bits=(1 << 23) + 1), dict(num_columns=0),
+        dict(num_columns=65537), dict(synapses_per_column=0), dict(synapses_per_column=4097),
+        dict(winners=0), dict(winners=1025), dict(connected_q8=257), dict(inc_q8=300),
+        dict(dec_q8=257),
+    ]
+    for b in bad:
+        c = dict(good)
+        c.update(b)
+        with pytest.raises(sp.SpError) as e:
+            sp.sp_config_check(c)
+        assert e.value.code == sp.SP_EINVAL
+        assert sp.sp_frame_words(c) == 0 and sp.sp_workspace_bytes(c) == 0
+        assert sp.sp_last_error()
+
+
+def test_check_state_host():
+    cfg = synth.sp_config(100, 4, 8, 1, 2)
+    w = synth.random_instance(1, cfg, frames=1)
+    sp.sp_check_state_host(cfg, w.idx, w.perm)
+    idx = w.idx.copy()
+    idx[2, 3] = 100
+    with pytest.raises(sp.SpError, match=r"idx\[19\]=100"):
+        sp.sp_check_state_host(cfg, idx, w.perm)
+    for badp in (0.3, -1 / 256, 257 / 256, np.nan):
+        perm = w.perm.copy()
+        perm[1, 1] = badp
+        with pytest.raises(sp.SpError, match=r"perm\[9\]"):
+            sp.sp_check_state_host(cfg, w.idx, perm)
+
+
+def test_null_handle_and_args_are_rejected_on_host():
+    L = _native.lib()
+    assert L.sp_step(None, None, 0, 1, None, None, None) == sp.SP_EINVAL
+    assert L.sp_step_plain(None, None, 0, 1, None, None, None) == sp.SP_EINVAL
+    assert L.sp_sync(None, None) == sp.SP_EINVAL
+    assert L.sp_step_is_persistent(None) == sp.SP_EINVAL
+    assert L.sp_destroy(None) == sp.SP_OK
+    out = ctypes.c_void_p()
+    cfg = _native.SpConfig.from_dict(synth.sp_config(100, 4, 8, 1, 2))
+    assert L.sp_create(ctypes.byref(cfg), None, None, None, ctypes.byref(out)) == sp.SP_EINVAL
+    assert L.sp_create(None, None, None, None, ctypes.byref(out)) == sp.SP_EINVAL
+    assert out.value is None

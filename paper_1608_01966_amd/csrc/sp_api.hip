@@ -22,13 +22,13 @@ struct sp_handle {
   int device;
   void* ws;
   size_t ws_bytes;
-  uint32_t* xchg;      // [2][C]
+  uint32_t* xchg;      // [replicas][2][exchange entries] of 16 bits
   uint32_t* err;       // [1] (padded)
   uint32_t* check;     // [4]
   int32_t* ov_scratch; // [C]
   uint64_t xchg_frames;
   bool persistent;
-  uint32_t cpw, rpc, grid, rows;
+  uint32_t grid, replicas;
   const void* pkernel;
   size_t plds;
   bool broken;
@@ -67,7 +67,10 @@ struct WsLayout {
 WsLayout ws_layout(const sp_config& c) {
   WsLayout l;
   l.xchg = 0;
-  l.err = align_up(l.xchg + sizeof(uint32_t) * 2 * (size_t)c.num_columns, 256);
+  l.err = align_up(l.xchg + sizeof(uint16_t) * 2 * htmsp::kPersistMaxReplicas *
+                               htmsp::persistent_exchange_arrays() *
+                               (size_t)htmsp::persistent_exchange_entries(c.num_columns),
+                   256);
   l.check = align_up(l.err + sizeof(uint32_t), 256);
   l.ov = align_up(l.check + 4 * sizeof(uint32_t), 256);
   l.total = align_up(l.ov + sizeof(int32_t) * (size_t)c.num_columns, 256);
@@ -144,29 +147,36 @@ int check_step_args(const sp_handle* h, const uint32_t* frames, uint32_t F, int3
 // seconds; a correct launch needs a tiny fraction of it).
 constexpr uint32_t kSpinLimit = 1u << 21;
 
+uint32_t next_pow2(uint32_t x) {
+  uint32_t p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+// Chooses the persistent kernel instance: rows of 64 synapses per column
+// rounded up to a power of two, 16 rows per workgroup, exchange words per
+// lane for C; the grid must be co-resident.
 void plan_persistent(sp_handle* h) {
   h->persistent = false;
   int dev = h->device, cus = 0, coop = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return;
   if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess) return;
   const Shape& sh = h->sh;
-  if (!coop || cus <= 0 || sh.C > htmsp::kPersistMaxColumns) return;
-  const uint32_t rpc = (sh.S + 63) / 64;
-  uint32_t cpw = (sh.C + (uint32_t)cus - 1) / (uint32_t)cus;
-  if (cpw * rpc > (uint32_t)htmsp::kPersistMaxRows) cpw = (uint32_t)htmsp::kPersistMaxRows / rpc;
-  if (cpw == 0) return;
-  const uint32_t grid = (sh.C + cpw - 1) / cpw;
-  const uint32_t rows = cpw * rpc;
-  const void* k = htmsp::persistent_kernel(rows);
+  if (!coop || cus <= 0 || sh.C > htmsp::kPersistMaxColumns ||
+      sh.S > htmsp::kPersistMaxSynapses)
+    return;
+  const uint32_t rpc = next_pow2((sh.S + 63) / 64);
+  const uint32_t nv = next_pow2(htmsp::persistent_exchange_entries(sh.C) / 256);
+  const void* k = htmsp::persistent_kernel(rpc, nv);
   if (!k) return;
-  const size_t lds = htmsp::persistent_lds_bytes(sh);
+  const uint32_t cpw = htmsp::persistent_rows() / rpc;
+  const uint32_t grid = (sh.C + cpw - 1) / cpw;
+  const size_t lds = htmsp::persistent_lds_bytes();
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 64, lds) != hipSuccess) return;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 128, lds) != hipSuccess) return;
   if ((uint64_t)per_cu * (uint64_t)cus < grid) return;
-  h->cpw = cpw;
-  h->rpc = rpc;
   h->grid = grid;
-  h->rows = rows;
+  h->replicas = htmsp::kPersistReplicas;
   h->pkernel = k;
   h->plds = lds;
   h->persistent = true;
@@ -320,16 +330,15 @@ int sp_step(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames, int l
   a.F = num_frames;
   a.learn = learn ? 1u : 0u;
   a.frame_base = (uint32_t)h->xchg_frames;
-  a.cpw = h->cpw;
-  a.rpc = h->rpc;
+  a.replicas = h->replicas;
   a.spin_limit = kSpinLimit;
   a.sh = h->sh;
   void* args[] = {&a};
-  hipError_t e = hipLaunchCooperativeKernel(h->pkernel, dim3(h->grid), dim3(64), args,
+  hipError_t e = hipLaunchCooperativeKernel(h->pkernel, dim3(h->grid), dim3(128), args,
                                             (unsigned int)h->plds,
                                             static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "persistent step launch");
-  h->xchg_frames += num_frames;
+  h->xchg_frames += (num_frames + 1) / 2;
   return ok();
 }
 

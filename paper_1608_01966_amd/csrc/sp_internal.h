@@ -15,28 +15,41 @@ struct Shape {
   uint32_t theta, inc, dec; // connected threshold, increment, decrement (x256)
 };
 
-// Persistent multi-frame step: one workgroup (one wave) per group of `cpw`
-// consecutive columns, each column spread over `rpc` rows of 64 synapses.
+// Persistent multi-frame step: one workgroup (a main and a producer wave)
+// per group of `cpw` consecutive columns, each column spread over `rpc`
+// rows of 64 synapses.
 struct PersistArgs {
   const uint32_t* idx;
   float* perm;
   const uint32_t* frames;
   int32_t* ov_out;    // [F][C] or null
   int32_t* win_out;   // [F][k]
-  uint32_t* xchg;     // [2][C] tagged overlaps
+  uint32_t* xchg;     // [replicas][2][arrays][entries] 16-bit tagged overlaps
   uint32_t* err;      // set to non-zero when a wave gives up waiting
-  uint32_t F, learn, frame_base, cpw, rpc, spin_limit;
+  uint32_t F, learn, frame_base, replicas, spin_limit;  // frame_base counts exchanges
   Shape sh;
 };
 
-// Rows of 64 synapses one workgroup of the persistent kernel may hold.
-constexpr int kPersistMaxRows = 64;
-// Largest C the persistent kernel exchanges through LDS (uint16 per column).
-constexpr uint32_t kPersistMaxColumns = 16384;
+// Largest C the persistent kernel exchanges (16 64-bit words per lane).
+constexpr uint32_t kPersistMaxColumns = 4096;
+// Largest S it holds: 16 rows of 64 synapses per workgroup.
+constexpr uint32_t kPersistMaxSynapses = 1024;
+// Exchange copies the workspace holds (one per XCD at most), and the number
+// used: readers pick the copy of their XCD modulo this.
+constexpr uint32_t kPersistMaxReplicas = 8;
+constexpr uint32_t kPersistReplicas = 2;
 
-size_t persistent_lds_bytes(const Shape& sh);
-// The kernel instance for `rows` (rounded up to a power of two <= 64).
-const void* persistent_kernel(uint32_t rows);
+size_t persistent_lds_bytes();
+// Rows of 64 synapses one workgroup holds.
+uint32_t persistent_rows();
+// Exchange arrays per slot (frame t, frame t+1 if lost, frame t+1 if won).
+uint32_t persistent_exchange_arrays();
+// 16-bit exchange entries per array for C columns: 256 times the power of two
+// of 64-bit words per lane that covers C.
+uint32_t persistent_exchange_entries(uint32_t C);
+// The kernel instance for `rpc` rows per column (1, 2, 4, 8 or 16) and `nv`
+// 64-bit exchange words per lane (1, 2, 4, 8 or 16); nullptr otherwise.
+const void* persistent_kernel(uint32_t rpc, uint32_t nv);
 
 hipError_t launch_check_state(const uint32_t* idx, const float* perm, size_t n, uint32_t N,
                               uint32_t* out4, hipStream_t s);

@@ -189,218 +189,586 @@ __global__ __launch_bounds__(256) void k_learn_plain(const uint32_t* __restrict_
 }
 
 // ---------------------------------------------------------------------------
-// Persistent multi-frame step.  Workgroup g (one wave) owns columns
-// [g*cpw, g*cpw + ncols); row r of its register state holds synapses
-// (r % rpc)*64 + lane of local column r / rpc, packed as idx << 9 | q.
-constexpr uint32_t kPollBatch = 16;
+// Persistent multi-frame step.
+//
+// Workgroup g (two waves) owns CPW = kRows / RPC consecutive columns from
+// g*CPW; row r holds synapses (r % RPC)*64 + lane of local column r / RPC.
+//   wave 0 (main) keeps the synapse state in registers for the whole launch
+//     (idx << 9 | q, plus the mask of the input bit when connected) and, per
+//     frame: overlap of its columns, publish, collect every column's
+//     overlap, resolve the global top-k, learn on its winning columns, and
+//     write the previous frame's outputs while the exchange is in flight.
+//   wave 1 (producer) gathers the input words the group's synapses need, up
+//     to kRing - 1 frames ahead, into an LDS ring, so that no gather latency
+//     sits in front of the main wave's exchange loads.
+// Exchange: one 16-bit entry [tag:2 | overlap:14] per column, written as
+// whole words with agent-scope stores into each of `replicas` copies and read with
+// agent-scope 64-bit loads (four columns each) from the copy of the reader's
+// XCD, so that readers spread over several memory channels.  Frame g of the
+// handle uses slot g & 1 and tag (g + 1) & 3; the slot's previous content
+// belongs to frame g - 2 with tag (g - 1) & 3 (or is the zeroed initial
+// state), so a stale entry is never taken for a fresh one, and a slot is
+// rewritten only after every workgroup has finished reading it.
+constexpr uint32_t kRows = 16;
+constexpr uint32_t kRing = 8;
+constexpr uint32_t kTagShift = 14;
+constexpr uint64_t kFieldBits = 0x3FFF3FFF3FFF3FFFull;
+constexpr uint64_t kTagBits = 0xC000C000C000C000ull;
+constexpr uint64_t kHighBits = 0x8000800080008000ull;
+constexpr uint64_t kOnes16 = 0x0001000100010001ull;
 
-template <int ROWS>
-__global__ __launch_bounds__(64) void k_sp_persistent(PersistArgs a) {
-  extern __shared__ uint32_t lds[];
-  const Shape sh = a.sh;
-  uint16_t* ovs = reinterpret_cast<uint16_t*>(lds);  // [C] overlaps of the frame
-  uint32_t* hist = lds + ((sh.C + 1) / 2);            // [S + 1] overlap histogram
-  const uint32_t lane = threadIdx.x;
-  const uint32_t c_begin = blockIdx.x * a.cpw;
-  const uint32_t ncols = min(a.cpw, sh.C - c_begin);
-  const uint32_t nrows = ncols * a.rpc;
+constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
 
-  // Invalid slots (past S, or past the workgroup's last column) load from
-  // offset 0 and are masked out by `valid`, so no load depends on a branch.
-  uint32_t st[ROWS], wc[ROWS], wn[ROWS];
-  uint64_t valid = 0;  // bit r: this lane holds a synapse in row r
-  {
-    uint32_t j = 0, rr = 0;
+__device__ __forceinline__ uint32_t lds_acquire(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ void lds_release(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ void store_entry(uint16_t* p, uint16_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void store_half(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void store_word(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint64_t load_entries(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint32_t xcc_id() {
+  uint32_t v;
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(v));
+  return v;
+}
+
+// Fields of w (four 16-bit fields holding values < 2^14) that are >= x,
+// for 1 <= x <= 2^14: field + 0x8000 - x reaches bit 15 exactly when
+// field >= x, and never carries into the next field.
+__device__ __forceinline__ uint32_t fields_ge(uint64_t w, uint32_t x, uint64_t keep) {
+  return (uint32_t)__popcll((w + (uint64_t)(0x8000u - x) * kOnes16) & keep);
+}
+
+// Sum over the wave of per-lane counts below 2^BITS, one ballot per bit.
+template <int BITS>
+__device__ __forceinline__ uint32_t wave_count(uint32_t v) {
+  uint32_t s = 0;
 #pragma unroll
-    for (int r = 0; r < ROWS; ++r) {
-      const uint32_t s = rr * kWave + lane;
-      const bool ok = (uint32_t)r < nrows && s < sh.S;
-      const size_t off = ok ? (size_t)(c_begin + j) * sh.S + s : 0;
-      const uint32_t i = min(a.idx[off], sh.N - 1);
-      const uint32_t packed = (i << 9) | perm_to_q(a.perm[off]);
-      st[r] = ok ? packed : 0u;
-      valid |= (uint64_t)ok << r;
-      if (++rr == a.rpc) { rr = 0; ++j; }
+  for (int b = 0; b < BITS; ++b) s += (uint32_t)__popcll(__ballot((v >> b) & 1u)) << b;
+  return s;
+}
+
+// Columns (all, or only those below c_end) whose overlap is >= x.  Word u
+// of this lane holds columns u*256 + 4*lane + {0, 1, 2, 3}.
+template <int NV>
+__device__ __forceinline__ uint32_t count_ge(const uint64_t (&ev)[NV], uint32_t x) {
+  uint32_t n = 0;
+#pragma unroll
+  for (int u = 0; u < NV; ++u) n += fields_ge(ev[u], x, kHighBits);
+  return wave_count<ilog2(4 * NV) + 1>(n);
+}
+
+template <int NV>
+__device__ __forceinline__ uint32_t count_ge_before(const uint64_t (&ev)[NV], uint32_t x,
+                                                    uint32_t lane, uint32_t c_end) {
+  uint32_t n = 0;
+#pragma unroll
+  for (int u = 0; u < NV; ++u) {
+    const uint32_t cb = (uint32_t)u * 4 * kWave + 4 * lane;
+    const uint32_t nin = c_end > cb ? min(4u, c_end - cb) : 0u;
+    const uint64_t keep = nin >= 4 ? kHighBits : (((1ull << (16 * nin)) - 1ull) & kHighBits);
+    n += fields_ge(ev[u], x, keep);
+  }
+  return wave_count<ilog2(4 * NV) + 1>(n);
+}
+
+// Tag bits to check in exchange word u of this lane (entries at or past C
+// are never written and are skipped).
+__device__ __forceinline__ uint64_t tag_mask(uint32_t u, uint32_t lane, uint32_t C) {
+  const uint32_t cb = u * 4 * kWave + 4 * lane;
+  if (cb + 4 <= C) return kTagBits;
+  const uint32_t n = C > cb ? C - cb : 0u;
+  return ((1ull << (16 * n)) - 1ull) & kTagBits;
+}
+
+// Exclusive prefix over lanes of per-lane counts below 2^BITS.
+template <int BITS>
+__device__ __forceinline__ uint32_t wave_prefix(uint32_t v, uint32_t lane) {
+  const uint64_t lt = lanemask_lt(lane);
+  uint32_t s = 0;
+#pragma unroll
+  for (int b = 0; b < BITS; ++b) s += (uint32_t)__popcll(__ballot((v >> b) & 1u) & lt) << b;
+  return s;
+}
+
+// Field masks of the winners among all columns of one frame: every field
+// above T, and the first `need` fields equal to T in column order (word u,
+// lane l, field q is column u*256 + 4*l + q).  T == 0 selects every
+// positive field.
+template <int NV>
+__device__ __forceinline__ void select_all(const uint64_t (&ev)[NV], uint32_t T, uint32_t need,
+                                           uint32_t lane, uint64_t (&fm)[NV]) {
+  const uint64_t k_gt = (uint64_t)(0x8000u - (T + 1)) * kOnes16;
+  const uint64_t k_ge = (uint64_t)(0x8000u - T) * kOnes16;
+  uint32_t before = 0;  // fields equal to T in earlier words, whole wave
+#pragma unroll
+  for (int u = 0; u < NV; ++u) {
+    const uint64_t gt = (ev[u] + k_gt) & kHighBits;
+    const uint64_t eq = T ? (((ev[u] + k_ge) & kHighBits) & ~gt) : 0ull;
+    const uint32_t n = (uint32_t)__popcll(eq);
+    const uint32_t pre = before + wave_prefix<3>(n, lane);
+    uint32_t keep = need > pre ? need - pre : 0u;
+    uint64_t take = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint64_t bit = eq & (0x8000ull << (16 * q));
+      const bool use = bit != 0ull && keep > 0;
+      take |= use ? bit : 0ull;
+      keep -= use ? 1u : 0u;
     }
+    fm[u] = ((gt | take) >> 15) * 0xFFFFull;
+    before += wave_count<3>(n);
+  }
+}
+
+// Own columns: overlaps of this group's columns for one frame (Algorithm 1,
+// gated at min_overlap), as wave-uniform values.
+template <int RPC, int CPW>
+__device__ __forceinline__ void group_overlaps(const uint32_t (&w)[kRows],
+                                               const uint32_t (&msk)[kRows], uint32_t ncols,
+                                               uint32_t m, uint32_t (&ovs)[CPW]) {
 #pragma unroll
-    for (int r = 0; r < ROWS; ++r) {
-      wc[r] = a.frames[(st[r] >> 9) >> 5];
-      wn[r] = 0;
+  for (uint32_t j = 0; j < (uint32_t)CPW; ++j) {
+    uint32_t raw = 0;
+#pragma unroll
+    for (uint32_t rr = 0; rr < (uint32_t)RPC; ++rr)
+      raw += (uint32_t)__popcll(__ballot((w[j * RPC + rr] & msk[j * RPC + rr]) != 0u));
+    ovs[j] = (j < ncols && raw >= m) ? raw : 0u;
+  }
+}
+
+template <int CPW>
+__device__ __forceinline__ uint32_t lane_value(const uint32_t (&ovs)[CPW], uint32_t lane) {
+  uint32_t v = 0;
+#pragma unroll
+  for (uint32_t j = 0; j < (uint32_t)CPW; ++j) v = lane == j ? ovs[j] : v;
+  return v;
+}
+
+// Global top-k threshold (Algorithm 2, global form): T = the largest x >= 1
+// with #(overlap >= x) >= k, or 0 when fewer than k overlaps are positive;
+// *c_hi = #(overlap >= T + 1).  Invariant: #(overlap >= lo) >= k unless
+// lo == 0, and c_hi = #(overlap >= hi + 1) < k.  A gallop from `guess`
+// narrows [lo, hi], a binary search finishes it.
+template <int NV>
+__device__ __forceinline__ uint32_t topk_threshold(const uint64_t (&ev)[NV], uint32_t S,
+                                                   uint32_t k, uint32_t guess, uint32_t* c_hi_out) {
+  uint32_t lo = 0, hi = S, c_hi = 0;
+  const uint32_t g0 = min(max(guess, 1u), S);
+  const uint32_t c0 = count_ge(ev, g0);
+  if (c0 >= k) {
+    lo = g0;
+    for (uint32_t step = 1; lo < hi; step <<= 1) {
+      const uint32_t x = min(lo + step, hi);
+      const uint32_t cx = count_ge(ev, x);
+      if (cx >= k) {
+        lo = x;
+      } else {
+        hi = x - 1;
+        c_hi = cx;
+        break;
+      }
+    }
+  } else {
+    hi = g0 - 1;
+    c_hi = c0;
+    for (uint32_t step = 1; hi > 0; step <<= 1) {
+      const uint32_t x = hi >= step ? hi - step + 1 : 1u;
+      const uint32_t cx = count_ge(ev, x);
+      if (cx >= k) {
+        lo = x;
+        break;
+      }
+      hi = x - 1;
+      c_hi = cx;
     }
   }
-  for (uint32_t v = lane; v <= sh.S; v += kWave) hist[v] = 0;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1) / 2;
+    const uint32_t c = count_ge(ev, mid);
+    if (c >= k) {
+      lo = mid;
+    } else {
+      hi = mid - 1;
+      c_hi = c;
+    }
+  }
+  *c_hi_out = c_hi;
+  return lo;
+}
+
+// Whether this lane's own column (overlap v, lane < ncols) wins: above T, or
+// equal to T and among the first `need` such columns in column order.
+template <int NV>
+__device__ __forceinline__ bool own_wins(const uint64_t (&ev)[NV], uint32_t v, bool mine,
+                                         uint32_t T, uint32_t need, uint32_t lane,
+                                         uint32_t c_begin) {
+  const bool gt = mine && v > T;
+  const bool eq = mine && T != 0 && v == T;
+  const uint64_t eqm = __ballot(eq);
+  if (eqm == 0ull) return gt;
+  const uint32_t eqb =
+      count_ge_before(ev, T, lane, c_begin) - count_ge_before(ev, T + 1, lane, c_begin);
+  return gt || (eq && eqb + (uint32_t)__popcll(eqm & lanemask_lt(lane)) < need);
+}
+
+// What one frame leaves for its deferred outputs.
+struct FrameResult {
+  uint32_t T, need, nsel, ov;
+  bool sel;
+};
+
+// Outputs of frame tt: overlaps of the own columns, the own winners at their
+// rank in column order, and (group 0) the -1 padding.
+template <int NV>
+__device__ __forceinline__ void write_frame(const PersistArgs& a, const uint64_t (&ev)[NV],
+                                            const FrameResult& r, uint32_t tt, uint32_t lane,
+                                            bool mine, uint32_t c_begin) {
+  const Shape& sh = a.sh;
+  if (a.ov_out && mine) a.ov_out[(size_t)tt * sh.C + c_begin + lane] = (int32_t)r.ov;
+  int32_t* wrow = a.win_out + (size_t)tt * sh.k;
+  if (blockIdx.x == 0)
+    for (uint32_t i = r.nsel + lane; i < sh.k; i += kWave) wrow[i] = -1;
+  if (__ballot(r.sel) != 0ull) {
+    const uint32_t gtb = count_ge_before(ev, r.T + 1, lane, c_begin);
+    const uint32_t eqb = r.T ? count_ge_before(ev, r.T, lane, c_begin) - gtb : 0u;
+    const uint32_t gt_pre =
+        gtb + (uint32_t)__popcll(__ballot(mine && r.ov > r.T) & lanemask_lt(lane));
+    const uint32_t eq_pre =
+        eqb + (uint32_t)__popcll(__ballot(mine && r.T != 0 && r.ov == r.T) & lanemask_lt(lane));
+    if (r.sel) wrow[gt_pre + min(eq_pre, r.need)] = (int32_t)(c_begin + lane);
+  }
+}
+
+// Persistent multi-frame step, two frames per exchange.  Learning makes
+// frame t + 1 depend on which columns win frame t, but only through the
+// winners' own synapses; so each group publishes, with its frame-t
+// overlaps, the frame-(t+1) overlaps its columns will have if they lose
+// frame t and if they win it.  Every group resolves frame t's winners,
+// picks each column's frame-(t+1) overlap accordingly and resolves frame
+// t + 1 as well, so one exchange round trip serves two frames; the results
+// are exactly those of stepping the frames one by one.
+template <int RPC, int NV>
+__global__ __launch_bounds__(128) void k_sp_persistent(PersistArgs a) {
+  constexpr uint32_t CPW = kRows / RPC;
+  constexpr uint32_t CPAD = NV * 4 * kWave;  // entries per exchange array
+  constexpr uint32_t NARR = 3;               // frame t, frame t+1 if lost, if won
+  extern __shared__ uint32_t lds[];
+  uint32_t* ring = lds;                         // [kRing][kRows][64] input words
+  uint32_t* ctl = lds + kRing * kRows * kWave;  // [0] produced, [1] consumed, [2] abort
+  const Shape sh = a.sh;
+  const uint32_t lane = threadIdx.x % kWave;
+  const uint32_t c_begin = blockIdx.x * CPW;
+  const uint32_t ncols = min(CPW, sh.C - c_begin);
+
+  if (threadIdx.x == 0) {
+    ctl[0] = 0;
+    ctl[1] = 0;
+    ctl[2] = 0;
+  }
   __syncthreads();
 
+  if (threadIdx.x >= kWave) {
+    // ---- producer wave ----
+    uint32_t wi[kRows];
+#pragma unroll
+    for (uint32_t r = 0; r < kRows; ++r) {
+      const uint32_t j = r / RPC, s = (r % RPC) * kWave + lane;
+      const bool ok = j < ncols && s < sh.S;
+      const size_t off = ok ? (size_t)(c_begin + j) * sh.S + s : 0;
+      wi[r] = ok ? min(a.idx[off], sh.N - 1) >> 5 : 0u;
+    }
+    for (uint32_t t = 0; t < a.F; ++t) {
+      uint32_t spins = 0;
+      while (lds_acquire(&ctl[1]) + kRing <= t) {
+        if (lds_acquire(&ctl[2]) != 0 || ++spins > a.spin_limit) {
+          lds_release(&ctl[2], 1u);
+          return;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+      const uint32_t* fr = a.frames + (size_t)t * sh.W;
+      uint32_t w[kRows];
+#pragma unroll
+      for (uint32_t r = 0; r < kRows; ++r) w[r] = fr[wi[r]];
+      uint32_t* dst = ring + (t % kRing) * kRows * kWave + lane;
+#pragma unroll
+      for (uint32_t r = 0; r < kRows; ++r) dst[r * kWave] = w[r];
+      lds_release(&ctl[0], t + 1);
+    }
+    return;
+  }
+
+  // ---- main wave ----
+  uint32_t st[kRows], msk[kRows];
+#pragma unroll
+  for (uint32_t r = 0; r < kRows; ++r) {
+    const uint32_t j = r / RPC, s = (r % RPC) * kWave + lane;
+    const bool ok = j < ncols && s < sh.S;
+    const size_t off = ok ? (size_t)(c_begin + j) * sh.S + s : 0;
+    const uint32_t i = min(a.idx[off], sh.N - 1);
+    const uint32_t q = perm_to_q(a.perm[off]);
+    st[r] = ok ? (i << 9) | q : 0u;
+    msk[r] = (ok && q >= sh.theta) ? (1u << (i & 31u)) : 0u;
+  }
+  // Rows that hold a synapse in this lane.
+  uint32_t row_ok = 0;
+#pragma unroll
+  for (uint32_t r = 0; r < kRows; ++r)
+    row_ok |= ((r / RPC) < ncols && (r % RPC) * kWave + lane < sh.S) ? 1u << r : 0u;
+
+  uint16_t* x16 = reinterpret_cast<uint16_t*>(a.xchg);
+  uint32_t* x32w = a.xchg;
+  uint64_t* x64w = reinterpret_cast<uint64_t*>(a.xchg);
+  const uint64_t* x64 = x64w;
+  const uint32_t rep = xcc_id() % a.replicas;
+  const bool mine = lane < ncols;
+
+  uint64_t ev0[NV], ev1[NV];  // overlaps of the pair's two frames, tags stripped
+#pragma unroll
+  for (int u = 0; u < NV; ++u) {
+    ev0[u] = 0;
+    ev1[u] = 0;
+  }
+  uint32_t guess = 1 + sh.S / 16;
+  FrameResult r0 = {0, 0, 0, 0, false}, r1 = {0, 0, 0, 0, false};
   bool abort = false;
-  for (uint32_t t = 0; t < a.F && !abort; ++t) {
-    // Overlap of the own columns (Algorithm 1): lane j accumulates column j.
-    uint32_t myraw = 0;
+
+  // Publishes the group's CPW entries of exchange array `arr` as whole words
+  // (entries past C land in the padding that readers skip).
+  auto publish = [&](uint32_t slot, uint32_t arr, uint32_t tg, const uint32_t(&ovs)[CPW]) {
+    if constexpr (CPW >= 4) {
+      uint64_t word = 0;
+#pragma unroll
+      for (uint32_t q = 0; q < CPW / 4; ++q) {
+        const uint64_t wq = (uint64_t)(tg | ovs[4 * q]) | ((uint64_t)(tg | ovs[4 * q + 1]) << 16) |
+                            ((uint64_t)(tg | ovs[4 * q + 2]) << 32) |
+                            ((uint64_t)(tg | ovs[4 * q + 3]) << 48);
+        word = lane == q ? wq : word;
+      }
+      if (lane < CPW / 4)
+        for (uint32_t rr = 0; rr < a.replicas; ++rr)
+          store_word(x64w + (((size_t)(rr * 2 + slot) * NARR + arr) * CPAD + c_begin) / 4 + lane,
+                     word);
+    } else if constexpr (CPW == 2) {
+      if (lane == 0)
+        for (uint32_t rr = 0; rr < a.replicas; ++rr)
+          store_half(x32w + (((size_t)(rr * 2 + slot) * NARR + arr) * CPAD + c_begin) / 2,
+                     (tg | ovs[0]) | ((tg | ovs[1]) << 16));
+    } else {
+      if (lane == 0)
+        for (uint32_t rr = 0; rr < a.replicas; ++rr)
+          store_entry(x16 + ((size_t)(rr * 2 + slot) * NARR + arr) * CPAD + c_begin,
+                      (uint16_t)(tg | ovs[0]));
+    }
+  };
+
+  uint32_t prev_t = 0;
+  bool prev_two = false;
+  for (uint32_t t = 0; t < a.F; t += 2) {
+    const bool two = t + 1 < a.F;
+    const uint32_t nf = two ? 2u : 1u;
+    // Input words of the pair's frames from the producer.
     {
-      uint32_t j = 0, rr = 0;
-#pragma unroll
-      for (int r = 0; r < ROWS; ++r) {
-        const uint32_t i = st[r] >> 9, q = st[r] & 511u;
-        const bool hit = ((valid >> r) & 1ull) && q >= sh.theta && input_bit(wc[r], i);
-        const uint32_t pc = (uint32_t)__popcll(__ballot(hit));
-        myraw += lane == j ? pc : 0u;
-        if (++rr == a.rpc) { rr = 0; ++j; }
+      uint32_t spins = 0;
+      while (lds_acquire(&ctl[0]) < t + nf) {
+        if (lds_acquire(&ctl[2]) != 0 || ++spins > a.spin_limit) {
+          abort = true;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
       }
     }
-    const bool mine = lane < ncols;
-    const uint32_t my_ov = (mine && myraw >= sh.m) ? myraw : 0u;
-
-    // Publish, tagged with the frame's global sequence number.
-    const uint32_t g = a.frame_base + t;
-    const uint32_t tag = (g + 1u) & 0xFFFFu;
-    uint32_t* xs = a.xchg + (size_t)(g & 1u) * sh.C;
-    if (mine) store_tagged(xs + c_begin + lane, (tag << 16) | my_ov);
-
-    // Gather the next frame's input words while the others publish.
-    if (t + 1 < a.F) {
-      const uint32_t* fr = a.frames + (size_t)(t + 1) * sh.W;
+    if (abort) break;
+    uint32_t w0[kRows], w1[kRows];
+    {
+      const uint32_t* s0 = ring + (t % kRing) * kRows * kWave + lane;
+      const uint32_t* s1 = ring + ((t + 1) % kRing) * kRows * kWave + lane;
 #pragma unroll
-      for (int r = 0; r < ROWS; ++r) wn[r] = fr[(st[r] >> 9) >> 5];
-    }
-
-    // Collect every column's overlap and histogram the positive ones.
-    uint32_t spins = 0;
-    for (uint32_t base = 0; base < sh.C && !abort; base += kWave * kPollBatch) {
-      uint32_t v[kPollBatch];
-#pragma unroll
-      for (uint32_t u = 0; u < kPollBatch; ++u) {
-        const uint32_t c = base + u * kWave + lane;
-        v[u] = c < sh.C ? load_tagged(xs + c) : (tag << 16);
+      for (uint32_t r = 0; r < kRows; ++r) {
+        w0[r] = s0[r * kWave];
+        w1[r] = two ? s1[r * kWave] : 0u;
       }
+    }
+    lds_release(&ctl[1], t + nf);
+
+    // Frame t's overlaps; frame t + 1's if each column loses frame t (same
+    // state) and if it wins it (state after learning frame t).
+    uint32_t ov0[CPW], ovL[CPW], ovW[CPW];
+    uint32_t stW[kRows], mskW[kRows];
+    group_overlaps<RPC, CPW>(w0, msk, ncols, sh.m, ov0);
+#pragma unroll
+    for (uint32_t r = 0; r < kRows; ++r) {
+      const uint32_t i = st[r] >> 9;
+      const uint32_t q = learn_q(st[r] & 511u, input_bit(w0[r], i), sh);
+      const bool ok = a.learn && ((row_ok >> r) & 1u);  // no learning: both cases agree
+      stW[r] = ok ? (i << 9) | q : st[r];
+      mskW[r] = ok ? (q >= sh.theta ? 1u << (i & 31u) : 0u) : msk[r];
+    }
+    group_overlaps<RPC, CPW>(w1, msk, ncols, sh.m, ovL);
+    group_overlaps<RPC, CPW>(w1, mskW, ncols, sh.m, ovW);
+
+    // Publish into every replica.
+    const uint32_t g = a.frame_base + t / 2;
+    const uint32_t tag = (g + 1u) & 3u;
+    const uint32_t slot = g & 1u;
+    const uint32_t tg = tag << kTagShift;
+    publish(slot, 0, tg, ov0);
+    publish(slot, 1, tg, ovL);
+    publish(slot, 2, tg, ovW);
+
+    // Collect every column's entries from this XCD's replica; the previous
+    // pair's outputs are written while the first loads are in flight.
+    const uint64_t tagw = (uint64_t)tg * kOnes16;
+    const uint64_t* xs = x64 + (size_t)(rep * 2 + slot) * NARR * (CPAD / 4);
+    uint64_t v0[NV], vL[NV], vW[NV];
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+      v0[u] = load_entries(xs + u * kWave + lane);
+      vL[u] = load_entries(xs + CPAD / 4 + u * kWave + lane);
+      vW[u] = load_entries(xs + 2 * (CPAD / 4) + u * kWave + lane);
+    }
+    if (t > 0) {
+      write_frame(a, ev0, r0, prev_t, lane, mine, c_begin);
+      if (prev_two) write_frame(a, ev1, r1, prev_t + 1, lane, mine, c_begin);
+    }
+    {
+      uint32_t spins = 0;
       while (true) {
         bool ok = true;
 #pragma unroll
-        for (uint32_t u = 0; u < kPollBatch; ++u) ok = ok && (v[u] >> 16) == tag;
+        for (int u = 0; u < NV; ++u) {
+          const uint64_t tm = tag_mask(u, lane, sh.C);
+          ok = ok && ((v0[u] ^ tagw) & tm) == 0ull && ((vL[u] ^ tagw) & tm) == 0ull &&
+               ((vW[u] ^ tagw) & tm) == 0ull;
+        }
         if (__all(ok)) break;
         if (++spins > a.spin_limit || ((spins & 63u) == 0 && load_tagged(a.err) != 0)) {
           abort = true;
           break;
         }
 #pragma unroll
-        for (uint32_t u = 0; u < kPollBatch; ++u) {
-          const uint32_t c = base + u * kWave + lane;
-          if ((v[u] >> 16) != tag) v[u] = load_tagged(xs + c);
-        }
-      }
-      if (abort) break;
-#pragma unroll
-      for (uint32_t u = 0; u < kPollBatch; ++u) {
-        const uint32_t c = base + u * kWave + lane;
-        const uint32_t val = v[u] & 0xFFFFu;
-        if (c < sh.C) {
-          ovs[c] = (uint16_t)val;
-          if (val) atomicAdd(&hist[val], 1u);
+        for (int u = 0; u < NV; ++u) {
+          const uint64_t tm = tag_mask(u, lane, sh.C);
+          if (((v0[u] ^ tagw) & tm) != 0ull) v0[u] = load_entries(xs + u * kWave + lane);
+          if (((vL[u] ^ tagw) & tm) != 0ull) vL[u] = load_entries(xs + CPAD / 4 + u * kWave + lane);
+          if (((vW[u] ^ tagw) & tm) != 0ull)
+            vW[u] = load_entries(xs + 2 * (CPAD / 4) + u * kWave + lane);
         }
       }
     }
     if (abort) break;
-    __syncthreads();
 
-    // Threshold T: the largest x >= 1 with #(overlap >= x) >= k, else 0.
-    // Lane l sums the bins of values [1 + l*B, (l+1)*B]; a suffix scan over
-    // lanes gives #(overlap >= 1 + l*B).
-    const uint32_t B = (sh.S + kWave - 1) / kWave;
-    const uint32_t vlo = 1 + lane * B, vhi = min(sh.S, (lane + 1) * B);
-    uint32_t suf = 0;
-    for (uint32_t x = vlo; x <= vhi; ++x) suf += hist[x];
+    // Frame t: threshold, and which own columns win.
+    const uint32_t my0 = lane_value(ov0, lane);
 #pragma unroll
-    for (uint32_t off = 1; off < kWave; off <<= 1) {
-      const uint32_t y = __shfl_down(suf, off);
-      if (lane + off < kWave) suf += y;
-    }
-    const uint32_t npos = __shfl(suf, 0);
-    const uint64_t reach = __ballot(suf >= sh.k);
-    uint32_t T = 0, cnt_gt = npos;
-    if (reach) {
-      const uint32_t L = 63u - (uint32_t)__clzll(reach);
-      const uint32_t above_l = __shfl(suf, (int)min(L + 1, 63u));
-      uint32_t acc = (L == 63u) ? 0u : above_l;
-      const uint32_t lo = 1 + L * B, hi = min(sh.S, (L + 1) * B);
-      for (uint32_t x = hi; x >= lo; --x) {
-        const uint32_t h = hist[x];
-        if (acc + h >= sh.k) {
-          T = x;
-          cnt_gt = acc;
-          break;
-        }
-        acc += h;
-      }
-    }
-    const uint32_t need = T ? sh.k - cnt_gt : 0u;
-    const uint32_t nsel = T ? sh.k : npos;
+    for (int u = 0; u < NV; ++u) ev0[u] = v0[u] & kFieldBits;
+    uint32_t c_hi;
+    const uint32_t T0 = topk_threshold(ev0, sh.S, sh.k, guess, &c_hi);
+    r0.T = T0;
+    r0.need = T0 ? sh.k - c_hi : 0u;
+    r0.nsel = T0 ? sh.k : c_hi;
+    r0.ov = my0;
+    r0.sel = own_wins(ev0, my0, mine, T0, r0.need, lane, c_begin);
+    if (T0) guess = T0;
 
-    // Rank of the own columns among the winners, in column order.
-    uint32_t gtb = 0, eqb = 0;
-    for (uint32_t c = lane; c < c_begin; c += kWave) {
-      const uint32_t v = ovs[c];
-      gtb += v > T;
-      eqb += (T != 0) & (v == T);
+    // Frame t + 1: every column's overlap given frame t's winners.
+    if (two) {
+      uint64_t fm[NV];
+      select_all(ev0, T0, r0.need, lane, fm);
+#pragma unroll
+      for (int u = 0; u < NV; ++u)
+        ev1[u] = ((vL[u] & ~fm[u]) | (vW[u] & fm[u])) & kFieldBits;
+      const uint32_t my1 = r0.sel ? lane_value(ovW, lane) : lane_value(ovL, lane);
+      const uint32_t T1 = topk_threshold(ev1, sh.S, sh.k, guess, &c_hi);
+      r1.T = T1;
+      r1.need = T1 ? sh.k - c_hi : 0u;
+      r1.nsel = T1 ? sh.k : c_hi;
+      r1.ov = my1;
+      r1.sel = own_wins(ev1, my1, mine, T1, r1.need, lane, c_begin);
+      if (T1) guess = T1;
     }
-    gtb = wave_sum(gtb);
-    eqb = wave_sum(eqb);
-    const bool gt = mine && my_ov > T;
-    const bool eq = mine && T != 0 && my_ov == T;
-    const uint32_t gt_pre = gtb + (uint32_t)__popcll(__ballot(gt) & lanemask_lt(lane));
-    const uint32_t eq_pre = eqb + (uint32_t)__popcll(__ballot(eq) & lanemask_lt(lane));
-    const bool sel = gt || (eq && eq_pre < need);
-    int32_t* wrow = a.win_out + (size_t)t * sh.k;
-    if (sel) wrow[gt_pre + min(eq_pre, need)] = (int32_t)(c_begin + lane);
-    if (blockIdx.x == 0)
-      for (uint32_t i = nsel + lane; i < sh.k; i += kWave) wrow[i] = -1;
-    if (a.ov_out && mine) a.ov_out[(size_t)t * sh.C + c_begin + lane] = (int32_t)my_ov;
 
-    // Learning on the own winning columns, with the bits of this frame.
+    // Learning: columns that won frame t take the state learned from it,
+    // then columns that win frame t + 1 learn from that frame.
     if (a.learn) {
-      const uint64_t selm = __ballot(sel);
-      uint32_t j = 0, rr = 0;
+      const uint64_t sel0 = __ballot(r0.sel);
+      const uint64_t sel1 = two ? __ballot(r1.sel) : 0ull;
 #pragma unroll
-      for (int r = 0; r < ROWS; ++r) {
-        const bool upd = ((selm >> j) & 1ull) && ((valid >> r) & 1ull);
-        const uint32_t i = st[r] >> 9, q = st[r] & 511u;
-        st[r] = upd ? (i << 9) | learn_q(q, input_bit(wc[r], i), sh) : st[r];
-        if (++rr == a.rpc) { rr = 0; ++j; }
+      for (uint32_t r = 0; r < kRows; ++r) {
+        const uint32_t j = r / RPC;
+        const bool won0 = (sel0 >> j) & 1ull;
+        st[r] = won0 ? stW[r] : st[r];
+        msk[r] = won0 ? mskW[r] : msk[r];
+        if ((sel1 >> j) & 1ull) {
+          const uint32_t i = st[r] >> 9;
+          const uint32_t q = learn_q(st[r] & 511u, input_bit(w1[r], i), sh);
+          const bool ok = (row_ok >> r) & 1u;
+          st[r] = ok ? (i << 9) | q : st[r];
+          msk[r] = ok ? (q >= sh.theta ? 1u << (i & 31u) : 0u) : msk[r];
+        }
       }
     }
-    __syncthreads();
-    for (uint32_t v = lane; v <= sh.S; v += kWave) hist[v] = 0;
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < ROWS; ++r) wc[r] = wn[r];
+    prev_t = t;
+    prev_two = two;
   }
 
   if (abort) {
+    lds_release(&ctl[2], 1u);
     if (lane == 0) store_tagged(a.err, 1u);
     return;
   }
+  if (a.F > 0) {
+    write_frame(a, ev0, r0, prev_t, lane, mine, c_begin);
+    if (prev_two) write_frame(a, ev1, r1, prev_t + 1, lane, mine, c_begin);
+  }
   if (a.learn) {
-    uint32_t j = 0, rr = 0;
 #pragma unroll
-    for (int r = 0; r < ROWS; ++r) {
-      if ((valid >> r) & 1ull)
-        a.perm[(size_t)(c_begin + j) * sh.S + rr * kWave + lane] = q_to_perm(st[r] & 511u);
-      if (++rr == a.rpc) { rr = 0; ++j; }
+    for (uint32_t r = 0; r < kRows; ++r) {
+      const uint32_t j = r / RPC, s = (r % RPC) * kWave + lane;
+      if ((row_ok >> r) & 1u) a.perm[(size_t)(c_begin + j) * sh.S + s] = q_to_perm(st[r] & 511u);
     }
   }
 }
 
 }  // namespace
 
-size_t persistent_lds_bytes(const Shape& sh) {
-  return sizeof(uint32_t) * (((size_t)sh.C + 1) / 2 + (size_t)sh.S + 1);
+size_t persistent_lds_bytes() { return sizeof(uint32_t) * ((size_t)kRing * kRows * kWave + 4); }
+
+uint32_t persistent_rows() { return kRows; }
+
+uint32_t persistent_exchange_arrays() { return 3; }
+
+uint32_t persistent_exchange_entries(uint32_t C) {
+  uint32_t nv = 1;
+  while (nv * 4 * kWave < C) nv <<= 1;
+  return nv * 4 * kWave;
 }
 
-const void* persistent_kernel(uint32_t rows) {
-  if (rows <= 1) return reinterpret_cast<const void*>(&k_sp_persistent<1>);
-  if (rows <= 2) return reinterpret_cast<const void*>(&k_sp_persistent<2>);
-  if (rows <= 4) return reinterpret_cast<const void*>(&k_sp_persistent<4>);
-  if (rows <= 8) return reinterpret_cast<const void*>(&k_sp_persistent<8>);
-  if (rows <= 16) return reinterpret_cast<const void*>(&k_sp_persistent<16>);
-  if (rows <= 32) return reinterpret_cast<const void*>(&k_sp_persistent<32>);
-  if (rows <= 64) return reinterpret_cast<const void*>(&k_sp_persistent<64>);
+const void* persistent_kernel(uint32_t rpc, uint32_t nv) {
+#define HTMSP_PK(P, V) \
+  if (rpc == P && nv == V) return reinterpret_cast<const void*>(&k_sp_persistent<P, V>);
+#define HTMSP_PK_V(P) HTMSP_PK(P, 1) HTMSP_PK(P, 2) HTMSP_PK(P, 4) HTMSP_PK(P, 8) HTMSP_PK(P, 16)
+  HTMSP_PK_V(1) HTMSP_PK_V(2) HTMSP_PK_V(4) HTMSP_PK_V(8) HTMSP_PK_V(16)
+#undef HTMSP_PK_V
+#undef HTMSP_PK
   return nullptr;
 }
 

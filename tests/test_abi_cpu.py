@@ -37,7 +37,8 @@ def test_config_checks():
     good = synth.sp_config(518400, 1024, 256, 4, 40)
     sp.sp_config_check(good)
     assert sp.sp_frame_words(good) == 16200
-    assert sp.sp_workspace_bytes(good) >= 4 * 3 * 1024
+    # two exchange slots of 16-bit entries plus an int32 overlap scratch row
+    assert sp.sp_workspace_bytes(good) >= 2 * 2 * 1024 + 4 * 1024
     bad = [
         dict(input_bits=0), dict(input_bits=(1 << 23) + 1), dict(num_columns=0),
         dict(num_columns=65537), dict(synapses_per_column=0), dict(synapses_per_column=4097),

@@ -165,8 +165,16 @@ def test_parameter_extremes(case):
 
 
 def test_max_columns_persistent():
+    """4096 columns is the largest count the persistent exchange holds."""
+    cfg = synth.sp_config(50000, 4096, 64, 3, 400)
+    check(synth.random_instance(14, cfg, frames=6, density=0.1), expect_persistent=True)
+
+
+def test_columns_past_persistent_limit():
+    cfg = synth.sp_config(50000, 4097, 64, 3, 400)
+    check(synth.random_instance(14, cfg, frames=4, density=0.1), expect_persistent=False)
     cfg = synth.sp_config(50000, 16384, 64, 3, 400)
-    check(synth.random_instance(14, cfg, frames=4, density=0.1), expect_persistent=True)
+    check(synth.random_instance(14, cfg, frames=4, density=0.1), expect_persistent=False)
 
 
 def test_max_columns_plain_only():
@@ -176,7 +184,15 @@ def test_max_columns_plain_only():
 
 def test_max_synapses():
     cfg = synth.sp_config(100000, 40, 4096, 10, 8)
-    check(synth.random_instance(16, cfg, frames=5, density=0.05), expect_persistent=True)
+    check(synth.random_instance(16, cfg, frames=5, density=0.05), expect_persistent=False)
+
+
+def test_max_synapses_persistent():
+    """1024 synapses (16 rows of 64) is the most one persistent workgroup holds."""
+    cfg = synth.sp_config(100000, 300, 1024, 10, 24)
+    check(synth.random_instance(18, cfg, frames=8, density=0.05), expect_persistent=True)
+    cfg = synth.sp_config(100000, 300, 1025, 10, 24)
+    check(synth.random_instance(18, cfg, frames=3, density=0.05), expect_persistent=False)
 
 
 def test_max_input_bits():

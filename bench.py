@@ -25,6 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+PROFILE = os.path.join(ROOT, "profiles", "k_sp_persistent_960x540_1024c_256s.md")
 
 
 def algorithmic_bytes(cfg: dict, winners: np.ndarray) -> int:
@@ -68,6 +69,9 @@ def main() -> int:
                     help="frames timed through the one-frame-per-launch path (0: skip)")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibration-copy-mb", type=int, default=0,
+                    help="before timing, run one elementwise int32 copy of this many MiB "
+                         "(reads and writes that many bytes) to calibrate memory counters")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -86,6 +90,14 @@ def main() -> int:
     C, S, k = cfg["num_columns"], cfg["synapses_per_column"], cfg["winners"]
     frames = torch.from_numpy(np.ascontiguousarray(w.frames).view(np.int32)).cuda()
     F = frames.shape[0]
+
+    if args.calibration_copy_mb > 0:
+        n = args.calibration_copy_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.add(src, 1, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
 
     pool = sp.SpatialPooler(cfg, w.idx, w.perm)
     perm0 = pool.perm.clone()
@@ -126,6 +138,16 @@ def main() -> int:
     abytes = algorithmic_bytes(cfg, win_np)
     achieved = abytes / (kernel_ms * 1e-3) / 1e9
 
+    # Measured HBM traffic from the committed counter summary, only while the
+    # kernel source is the one the counters were taken from.
+    from paper_1608_01966_amd import profiling
+    traffic, traffic_bytes = None, None
+    blk = profiling.read_block(PROFILE)
+    if (blk and blk.get("source_sha256") == profiling.source_sha256()
+            and (C, S, F) == (1024, 256, 1000) and "hbm_bytes_per_launch" in blk):
+        traffic_bytes = blk["hbm_bytes_per_launch"]
+        traffic = traffic_bytes / (kernel_ms * 1e-3) / 1e9
+
     plain = None
     if args.plain_frames > 0:
         pf = min(args.plain_frames, F)
@@ -164,9 +186,10 @@ def main() -> int:
                    "path": "persistent" if pool.persistent else "plain"},
         "synapse_updates_per_s": fps * C * S,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_sp_persistent", "kernel_ms_per_launch": kernel_ms,
-                     "algorithmic_bytes_per_launch": abytes},
+                     "algorithmic_bytes_per_launch": abytes,
+                     "counter_bytes_per_launch": traffic_bytes},
         "plain_one_frame_per_launch_frames_per_s": plain,
         "cpu_baseline": cpu,
     }
@@ -176,4 +199,6 @@ def main() -> int:
 
 
 if __name__ == "__main__":
-    sys.exit(main())
+    rc = main()
+    if rc:
+        sys.exit(rc)

@@ -35,8 +35,10 @@
  * Ownership: idx and perm are caller-owned device buffers that the handle
  * borrows for its lifetime; the library reads idx and reads/writes perm in
  * place.  frames, overlaps and winners are caller-owned per call.  The
- * library allocates only a small per-handle workspace (sp_workspace_bytes)
- * in sp_create and frees it in sp_destroy.
+ * library allocates a small per-handle workspace (sp_workspace_bytes) in
+ * sp_create and, on the first sp_infer, the compacted connected lists
+ * (4 * (S * C + C) bytes) plus, when sp_infer gets no overlap buffer, an
+ * [F][C] scratch; sp_destroy frees all of it.
  *
  * Streams: `stream` is a hipStream_t (NULL = the null stream).  Steps are
  * enqueued and return at once; results are valid once the stream has
@@ -126,6 +128,22 @@ int sp_step(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames, int l
  * (overlap, inhibition, learning kernels per frame): the plain baseline. */
 int sp_step_plain(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames, int learn,
                   int32_t* overlaps_dev, int32_t* winners_dev, void* stream);
+
+/* Batched inference (Section 4.1's testing mode, learning off): overlap
+ * and global inhibition of F independent frames against the handle's
+ * current state, which is left unchanged.  Results equal sp_step with
+ * learn = 0 frame by frame.
+ *
+ * mode SP_INFER_GATHER compacts every column's connected synapses once per
+ * state change (a step that learned, or sp_check_state), then counts active
+ * inputs by gathering bits of each frame staged in LDS.  The first call
+ * after a state change synchronises `stream` (it reads back the longest
+ * connected list); SP_EINVAL if that list exceeds 256 synapses.
+ * overlaps may be NULL (the library then keeps an internal [F][C] buffer,
+ * grown on demand); winners must not be. */
+#define SP_INFER_GATHER 0
+int sp_infer(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames, int mode,
+             int32_t* overlaps_dev, int32_t* winners_dev, void* stream);
 
 /* 1 if sp_step runs this handle's shape as one persistent launch, 0 if it
  * runs the plain path, negative on a bad handle. */

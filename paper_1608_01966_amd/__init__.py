@@ -20,13 +20,15 @@ import ctypes
 import numpy as np
 
 from . import synth
-from ._native import (SP_EBROKEN, SP_EDEVICE, SP_EINVAL, SP_ENOMEM, SP_OK, SpConfig, lib)
+from ._native import (SP_EBROKEN, SP_EDEVICE, SP_EINVAL, SP_ENOMEM, SP_INFER_GATHER, SP_OK,
+                      SpConfig, lib)
 
 __all__ = [
     "SpError", "SpatialPooler", "synth", "sp_config_check", "sp_frame_words",
     "sp_workspace_bytes", "sp_check_state_host", "sp_create", "sp_check_state", "sp_step",
-    "sp_step_plain", "sp_step_is_persistent", "sp_sync", "sp_destroy", "sp_last_error",
-    "SP_OK", "SP_EINVAL", "SP_ENOMEM", "SP_EDEVICE", "SP_EBROKEN",
+    "sp_step_plain", "sp_infer", "sp_step_is_persistent", "sp_sync", "sp_destroy",
+    "sp_last_error", "SP_OK", "SP_EINVAL", "SP_ENOMEM", "SP_EDEVICE", "SP_EBROKEN",
+    "SP_INFER_GATHER",
 ]
 
 
@@ -136,6 +138,19 @@ def sp_step_plain(h: int, cfg, frames, learn: bool, overlaps, winners, stream=No
     _step(lib().sp_step_plain, "sp_step_plain", h, cfg, frames, learn, overlaps, winners, stream)
 
 
+def sp_infer(h: int, cfg, frames, mode: int, overlaps, winners, stream=None) -> None:
+    """Batched inference (learning off); overlaps may be None."""
+    import torch
+    c = _cfg(cfg)
+    F = int(frames.shape[0])
+    W = (c.input_bits + 31) // 32
+    pf = _dev(frames, torch.int32, (F, W), "frames")
+    po = _dev(overlaps, torch.int32, (F, c.num_columns), "overlaps")
+    pw = _dev(winners, torch.int32, (F, c.winners), "winners")
+    _check(lib().sp_infer(ctypes.c_void_p(h), pf, F, int(mode), po, pw, _stream(stream)),
+           "sp_infer")
+
+
 def sp_step_is_persistent(h: int) -> bool:
     return bool(_check(lib().sp_step_is_persistent(ctypes.c_void_p(h)), "sp_step_is_persistent"))
 
@@ -186,6 +201,20 @@ class SpatialPooler:
         win = torch.empty((F, self.cfg["winners"]), dtype=torch.int32, device=self.idx.device)
         fn = sp_step_plain if plain else sp_step
         fn(self.handle, self.cfg, frames, learn, ov, win, stream)
+        return ov, win
+
+    def infer(self, frames, overlaps: bool = True, mode: int = SP_INFER_GATHER, stream=None):
+        """Batched inference over F independent frames; returns (overlaps or
+        None, winners) GPU tensors; the state is not changed."""
+        import torch
+        if isinstance(frames, np.ndarray):
+            frames = torch.from_numpy(np.ascontiguousarray(frames, dtype=np.uint32).view(np.int32))
+        frames = frames.to(device=self.idx.device).contiguous()
+        F = frames.shape[0]
+        ov = torch.empty((F, self.cfg["num_columns"]), dtype=torch.int32,
+                         device=self.idx.device) if overlaps else None
+        win = torch.empty((F, self.cfg["winners"]), dtype=torch.int32, device=self.idx.device)
+        sp_infer(self.handle, self.cfg, frames, mode, ov, win, stream)
         return ov, win
 
     def sync(self, stream=None) -> None:

@@ -14,6 +14,7 @@ SP_OK, SP_EINVAL, SP_ENOMEM, SP_EDEVICE, SP_EBROKEN = 0, -1, -2, -3, -4
 SP_MAX_INPUT_BITS = 1 << 23
 SP_MAX_COLUMNS = 65536
 SP_MAX_SYNAPSES = 4096
+SP_INFER_GATHER = 0
 
 
 class SpConfig(ctypes.Structure):
@@ -46,6 +47,7 @@ SIGNATURES = [
     ("sp_check_state", ctypes.c_int, [P, P]),
     ("sp_step", ctypes.c_int, [P, P, U32, ctypes.c_int, P, P, P]),
     ("sp_step_plain", ctypes.c_int, [P, P, U32, ctypes.c_int, P, P, P]),
+    ("sp_infer", ctypes.c_int, [P, P, U32, ctypes.c_int, P, P, P]),
     ("sp_step_is_persistent", ctypes.c_int, [P]),
     ("sp_sync", ctypes.c_int, [P, P]),
     ("sp_destroy", ctypes.c_int, [P]),

@@ -32,6 +32,17 @@ struct sp_handle {
   const void* pkernel;
   size_t plds;
   bool broken;
+  int cus;
+  // Every learning step and every re-validation changes the state version;
+  // batched inference rebuilds its connected lists when the version moved.
+  uint64_t state_version;
+  uint32_t* infer_list;      // [S][C]
+  uint32_t* infer_cnt;       // [C]
+  uint32_t* infer_maxcnt;    // [1]
+  uint32_t infer_maxn;
+  uint64_t infer_version;    // state version the lists were built for (0: none)
+  int32_t* infer_ov;         // [capacity][C] overlaps when the caller wants none
+  uint32_t infer_ov_frames;
 };
 
 namespace {
@@ -279,6 +290,9 @@ int sp_create(const sp_config* cfg, uint32_t* idx_dev, float* perm_dev, void* st
     delete h;
     return rc;
   }
+  (void)hipDeviceGetAttribute(&h->cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (h->cus <= 0) h->cus = 1;
+  h->state_version = 1;
   plan_persistent(h);
   *out = h;
   return ok();
@@ -289,6 +303,7 @@ int sp_check_state(sp_handle* h, void* stream) {
   if (rc) return rc;
   DeviceScope ds(h->device);
   rc = run_check_state(h, static_cast<hipStream_t>(stream));
+  ++h->state_version;
   return rc ? rc : ok();
 }
 
@@ -299,6 +314,7 @@ int sp_step_plain(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames,
   DeviceScope ds(h->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
   const Shape& sh = h->sh;
+  if (learn && num_frames) ++h->state_version;
   for (uint32_t t = 0; t < num_frames; ++t) {
     const uint32_t* frame = frames_dev + (size_t)t * sh.W;
     int32_t* ov = overlaps_dev ? overlaps_dev + (size_t)t * sh.C : h->ov_scratch;
@@ -339,6 +355,71 @@ int sp_step(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames, int l
                                             static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "persistent step launch");
   h->xchg_frames += (num_frames + 1) / 2;
+  if (learn) ++h->state_version;
+  return ok();
+}
+
+int sp_infer(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames, int mode,
+             int32_t* overlaps_dev, int32_t* winners_dev, void* stream) {
+  int rc = check_step_args(h, frames_dev, num_frames, overlaps_dev, winners_dev);
+  if (rc) return rc;
+  if (mode != SP_INFER_GATHER) return fail(SP_EINVAL, "unknown inference mode %d", mode);
+  if (num_frames == 0) return ok();
+  DeviceScope ds(h->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const Shape& sh = h->sh;
+  hipError_t e = hipSuccess;
+  if (!h->infer_list) {
+    const size_t bytes = sizeof(uint32_t) * ((size_t)sh.S * sh.C + sh.C + 64);
+    e = hipMalloc(&h->infer_list, bytes);
+    if (e != hipSuccess) {
+      h->infer_list = nullptr;
+      return fail(SP_ENOMEM, "inference lists hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    }
+    h->infer_cnt = h->infer_list + (size_t)sh.S * sh.C;
+    h->infer_maxcnt = h->infer_cnt + sh.C;
+  }
+  if (h->infer_version != h->state_version) {
+    e = htmsp::launch_infer_prep(h->idx, h->perm, sh, h->infer_list, h->infer_cnt,
+                                 h->infer_maxcnt, s);
+    uint32_t maxn = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&maxn, h->infer_maxcnt, sizeof(maxn),
+                                            hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "inference prep");
+    h->infer_maxn = maxn;
+    h->infer_version = h->state_version;
+  }
+  if (h->infer_maxn > htmsp::infer_max_list())
+    return fail(SP_EINVAL, "a column has %u connected synapses; batched inference holds at most %u",
+                h->infer_maxn, htmsp::infer_max_list());
+  int32_t* ov = overlaps_dev;
+  if (!ov) {
+    if (h->infer_ov_frames < num_frames) {
+      if (h->infer_ov) {
+        e = hipFree(h->infer_ov);
+        h->infer_ov = nullptr;
+        h->infer_ov_frames = 0;
+        if (e != hipSuccess) return hip_fail(e, "inference scratch free");
+      }
+      const size_t bytes = sizeof(int32_t) * (size_t)num_frames * sh.C;
+      e = hipMalloc(&h->infer_ov, bytes);
+      if (e != hipSuccess) {
+        h->infer_ov = nullptr;
+        return fail(SP_ENOMEM, "inference scratch hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+      }
+      h->infer_ov_frames = num_frames;
+    }
+    ov = h->infer_ov;
+  }
+  e = htmsp::launch_infer_gather(h->infer_maxn, frames_dev, num_frames, h->infer_list,
+                                 h->infer_cnt, sh, ov, (uint32_t)h->cus, s);
+  if (e != hipSuccess) return hip_fail(e, "inference gather launch");
+  if (sh.C <= htmsp::kPersistMaxColumns)
+    e = htmsp::launch_topk_batch(ov, num_frames, sh, winners_dev, s);
+  else
+    e = htmsp::launch_topk_plain(ov, winners_dev, sh, s, num_frames);
+  if (e != hipSuccess) return hip_fail(e, "inference top-k launch");
   return ok();
 }
 
@@ -373,6 +454,8 @@ int sp_destroy(sp_handle* h) {
     DeviceScope ds(h->device);
     hipError_t e = hipDeviceSynchronize();
     if (e == hipSuccess) e = hipFree(h->ws);
+    if (e == hipSuccess && h->infer_list) e = hipFree(h->infer_list);
+    if (e == hipSuccess && h->infer_ov) e = hipFree(h->infer_ov);
     if (e != hipSuccess) rc = hip_fail(e, "destroy");
   }
   delete h;

@@ -1,0 +1,220 @@
+// Batched inference: F independent frames through a spatial pooler whose
+// state is frozen (learning off, Section 4.1's testing mode), overlap and
+// inhibition per frame (Section 1.1, Algorithms 1 and 2, global form).
+//
+// With learning off every frame sees the same connected synapses, so a prep
+// kernel compacts each column's connected inputs once into a slot-major list.
+// The gather kernel then holds one column per thread, its list in registers,
+// stages one whole frame at a time in LDS (a 960x540 frame is 64 800 B), and
+// counts the connected inputs that are on with one LDS read each; the
+// workgroups that share a frame run on one XCD so its L2 serves them all.
+// A second kernel resolves the global top-k of every frame, one wave per
+// frame, on overlaps packed four per 64-bit word.
+#include "sp_device.h"
+#include "sp_internal.h"
+
+namespace htmsp {
+
+namespace {
+
+using namespace dev;
+
+constexpr uint32_t kInferThreads = 256;
+
+// Column c's connected inputs, slot-major: list[i * C + c] for i < cnt[c];
+// slots from cnt[c] to S - 1 hold `pad`, a pixel whose word is always 0.
+__global__ __launch_bounds__(256) void k_infer_prep(const uint32_t* __restrict__ idx,
+                                                    const float* __restrict__ perm, Shape sh,
+                                                    uint32_t pad, uint32_t* __restrict__ list,
+                                                    uint32_t* __restrict__ cnt,
+                                                    uint32_t* __restrict__ maxcnt) {
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= sh.C) return;
+  uint32_t n = 0;
+  for (uint32_t s = 0; s < sh.S; ++s) {
+    const size_t off = (size_t)c * sh.S + s;
+    if (perm_to_q(perm[off]) >= sh.theta) list[(size_t)n++ * sh.C + c] = min(idx[off], sh.N - 1);
+  }
+  cnt[c] = n;
+  for (uint32_t i = n; i < sh.S; ++i) list[(size_t)i * sh.C + c] = pad;
+  atomicMax(maxcnt, n);
+}
+
+// Gather overlaps.  Block b serves column block cb (kInferThreads columns)
+// for frame group fg; the col_blocks blocks of one frame group get ids that
+// are equal modulo 8, i.e. run on one XCD.  LDS == true stages each frame
+// (W words plus the zero padding word) in LDS; otherwise words are read
+// from global memory (frames too large for LDS).
+template <int MAXN, bool LDS>
+__global__ __launch_bounds__(kInferThreads) void k_infer_gather(
+    const uint32_t* __restrict__ frames, uint32_t F, const uint32_t* __restrict__ list,
+    const uint32_t* __restrict__ cnt, Shape sh, uint32_t frames_per_group, uint32_t col_blocks,
+    uint32_t groups, int32_t* __restrict__ ov_out) {
+  extern __shared__ uint32_t fr[];
+  const uint32_t per = 8 * col_blocks;
+  const uint32_t fg = (blockIdx.x / per) * 8 + blockIdx.x % 8;
+  const uint32_t cb = (blockIdx.x % per) / 8;
+  if (fg >= groups) return;
+  const uint32_t c = cb * kInferThreads + threadIdx.x;
+  const bool col_ok = c < sh.C;
+  const uint32_t pad = sh.W * 32;
+
+  uint32_t lst[MAXN];
+#pragma unroll
+  for (int i = 0; i < MAXN; ++i)
+    lst[i] = (col_ok && (uint32_t)i < sh.S) ? list[(size_t)i * sh.C + c] : pad;
+  uint32_t n = col_ok ? cnt[c] : 0u;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) n = max(n, (uint32_t)__shfl_xor(n, off));
+
+  const uint32_t f0 = fg * frames_per_group;
+  const uint32_t f1 = min(F, f0 + frames_per_group);
+  for (uint32_t f = f0; f < f1; ++f) {
+    const uint32_t* frame = frames + (size_t)f * sh.W;
+    if constexpr (LDS) {
+      __syncthreads();
+      const uint32_t w4 = sh.W / 4;
+      const uint4* src = reinterpret_cast<const uint4*>(frame);
+      if ((reinterpret_cast<uintptr_t>(frame) & 15u) == 0) {
+        for (uint32_t i = threadIdx.x; i < w4; i += kInferThreads)
+          reinterpret_cast<uint4*>(fr)[i] = src[i];
+        for (uint32_t i = 4 * w4 + threadIdx.x; i < sh.W; i += kInferThreads) fr[i] = frame[i];
+      } else {
+        for (uint32_t i = threadIdx.x; i < sh.W; i += kInferThreads) fr[i] = frame[i];
+      }
+      if (threadIdx.x == 0) fr[sh.W] = 0u;
+      __syncthreads();
+    }
+    uint32_t acc = 0;
+#pragma unroll
+    for (int i0 = 0; i0 < MAXN; i0 += 16) {
+      if ((uint32_t)i0 < n) {
+#pragma unroll
+        for (int i = i0; i < i0 + 16; ++i) {
+          const uint32_t p = lst[i];
+          const uint32_t wi = p >> 5;
+          const uint32_t word = LDS ? fr[wi] : (wi < sh.W ? frame[wi] : 0u);
+          acc += input_bit(word, p);
+        }
+      }
+    }
+    if (col_ok) ov_out[(size_t)f * sh.C + c] = acc >= sh.m ? (int32_t)acc : 0;
+  }
+}
+
+// Global top-k of each frame (one wave per frame): overlaps packed four per
+// 64-bit word, the threshold by count probes, winners compacted in column
+// order, -1 padding.
+template <int NV>
+__global__ __launch_bounds__(256) void k_topk_batch(const int32_t* __restrict__ ov, uint32_t F,
+                                                    Shape sh, int32_t* __restrict__ winners) {
+  const uint32_t f = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  const uint32_t lane = threadIdx.x % kWave;
+  if (f >= F) return;
+  const int32_t* o = ov + (size_t)f * sh.C;
+  uint64_t ev[NV];
+#pragma unroll
+  for (int u = 0; u < NV; ++u) {
+    uint64_t w = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < 4; ++q) {
+      const uint32_t c = (uint32_t)u * 4 * kWave + 4 * lane + q;
+      const uint32_t v = c < sh.C ? (uint32_t)o[c] : 0u;
+      w |= (uint64_t)v << (16 * q);
+    }
+    ev[u] = w;
+  }
+  uint32_t c_hi;
+  const uint32_t T = topk_threshold(ev, sh.S, sh.k, 1 + sh.S / 16, &c_hi);
+  const uint32_t need = T ? sh.k - c_hi : 0u;
+  const uint32_t nsel = T ? sh.k : c_hi;
+  uint64_t fm[NV];
+  select_all(ev, T, need, lane, fm);
+  int32_t* wrow = winners + (size_t)f * sh.k;
+  uint32_t base = 0;
+#pragma unroll
+  for (int u = 0; u < NV; ++u) {
+    const uint64_t sel = fm[u] & kHighBits;
+    const uint32_t n = (uint32_t)__popcll(sel);
+    uint32_t pos = base + wave_prefix<3>(n, lane);
+#pragma unroll
+    for (uint32_t q = 0; q < 4; ++q) {
+      if (sel & (0x8000ull << (16 * q))) {
+        wrow[pos] = (int32_t)((uint32_t)u * 4 * kWave + 4 * lane + q);
+        ++pos;
+      }
+    }
+    base += wave_count<3>(n);
+  }
+  for (uint32_t i = nsel + lane; i < sh.k; i += kWave) wrow[i] = -1;
+}
+
+template <int MAXN, bool LDS>
+hipError_t launch_gather_t(const uint32_t* frames, uint32_t F, const uint32_t* list,
+                           const uint32_t* cnt, const Shape& sh, int32_t* ov, uint32_t cus,
+                           hipStream_t s) {
+  const uint32_t col_blocks = (sh.C + kInferThreads - 1) / kInferThreads;
+  // about two blocks per CU, frame groups a multiple of 8
+  uint32_t groups = (2 * cus + col_blocks - 1) / col_blocks;
+  groups = min(groups, F);
+  const uint32_t fpg = (F + groups - 1) / groups;
+  groups = (F + fpg - 1) / fpg;
+  const uint32_t padded = (groups + 7) / 8 * 8;
+  const size_t lds = LDS ? sizeof(uint32_t) * ((size_t)sh.W + 1) : 0;
+  hipLaunchKernelGGL((k_infer_gather<MAXN, LDS>), dim3(padded * col_blocks), dim3(kInferThreads),
+                     lds, s, frames, F, list, cnt, sh, fpg, col_blocks, groups, ov);
+  return hipGetLastError();
+}
+
+template <bool LDS>
+hipError_t launch_gather_l(uint32_t maxn, const uint32_t* frames, uint32_t F,
+                           const uint32_t* list, const uint32_t* cnt, const Shape& sh,
+                           int32_t* ov, uint32_t cus, hipStream_t s) {
+  if (maxn <= 32) return launch_gather_t<32, LDS>(frames, F, list, cnt, sh, ov, cus, s);
+  if (maxn <= 64) return launch_gather_t<64, LDS>(frames, F, list, cnt, sh, ov, cus, s);
+  if (maxn <= 96) return launch_gather_t<96, LDS>(frames, F, list, cnt, sh, ov, cus, s);
+  if (maxn <= 128) return launch_gather_t<128, LDS>(frames, F, list, cnt, sh, ov, cus, s);
+  if (maxn <= 160) return launch_gather_t<160, LDS>(frames, F, list, cnt, sh, ov, cus, s);
+  if (maxn <= 192) return launch_gather_t<192, LDS>(frames, F, list, cnt, sh, ov, cus, s);
+  if (maxn <= 224) return launch_gather_t<224, LDS>(frames, F, list, cnt, sh, ov, cus, s);
+  return launch_gather_t<256, LDS>(frames, F, list, cnt, sh, ov, cus, s);
+}
+
+}  // namespace
+
+uint32_t infer_max_list() { return 256; }
+
+size_t infer_lds_limit() { return 65536; }
+
+hipError_t launch_infer_prep(const uint32_t* idx, const float* perm, const Shape& sh,
+                             uint32_t* list, uint32_t* cnt, uint32_t* maxcnt, hipStream_t s) {
+  hipError_t e = hipMemsetAsync(maxcnt, 0, sizeof(uint32_t), s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_infer_prep, dim3((sh.C + 255) / 256), dim3(256), 0, s, idx, perm, sh,
+                     sh.W * 32, list, cnt, maxcnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_infer_gather(uint32_t maxn, const uint32_t* frames, uint32_t F,
+                               const uint32_t* list, const uint32_t* cnt, const Shape& sh,
+                               int32_t* ov, uint32_t cus, hipStream_t s) {
+  const bool lds = sizeof(uint32_t) * ((size_t)sh.W + 1) <= infer_lds_limit();
+  return lds ? launch_gather_l<true>(maxn, frames, F, list, cnt, sh, ov, cus, s)
+             : launch_gather_l<false>(maxn, frames, F, list, cnt, sh, ov, cus, s);
+}
+
+hipError_t launch_topk_batch(const int32_t* ov, uint32_t F, const Shape& sh, int32_t* winners,
+                             hipStream_t s) {
+  const uint32_t blocks = (F + 3) / 4;
+  const uint32_t nv = (sh.C + 255) / 256;
+#define HTMSP_TB(V)                                                                         \
+  if (nv <= V) {                                                                            \
+    hipLaunchKernelGGL(k_topk_batch<V>, dim3(blocks), dim3(256), 0, s, ov, F, sh, winners); \
+    return hipGetLastError();                                                               \
+  }
+  HTMSP_TB(1) HTMSP_TB(2) HTMSP_TB(4) HTMSP_TB(8) HTMSP_TB(16)
+#undef HTMSP_TB
+  return hipErrorInvalidValue;
+}
+
+}  // namespace htmsp

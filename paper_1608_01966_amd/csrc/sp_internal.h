@@ -55,8 +55,27 @@ hipError_t launch_check_state(const uint32_t* idx, const float* perm, size_t n, 
                               uint32_t* out4, hipStream_t s);
 hipError_t launch_overlap_plain(const uint32_t* idx, const float* perm, const uint32_t* frame,
                                 int32_t* ov, const Shape& sh, hipStream_t s);
-hipError_t launch_topk_plain(const int32_t* ov, int32_t* winners, const Shape& sh, hipStream_t s);
+// Top-k of `frames` consecutive frames (overlaps [frames][C], winners
+// [frames][k]), one workgroup per frame.
+hipError_t launch_topk_plain(const int32_t* ov, int32_t* winners, const Shape& sh, hipStream_t s,
+                             uint32_t frames = 1);
 hipError_t launch_learn_plain(const uint32_t* idx, float* perm, const uint32_t* frame,
                               const int32_t* winners, const Shape& sh, hipStream_t s);
+
+// Batched inference (sp_infer.hip).
+// Longest connected list the register-resident gather kernel holds.
+uint32_t infer_max_list();
+// Compacts every column's connected inputs into list [S][C] (slot-major,
+// padded with a pixel whose word is zero), counts in cnt [C], max in *maxcnt.
+hipError_t launch_infer_prep(const uint32_t* idx, const float* perm, const Shape& sh,
+                             uint32_t* list, uint32_t* cnt, uint32_t* maxcnt, hipStream_t s);
+// Overlaps [F][C] of F frames from the compacted lists (maxn <= infer_max_list()).
+hipError_t launch_infer_gather(uint32_t maxn, const uint32_t* frames, uint32_t F,
+                               const uint32_t* list, const uint32_t* cnt, const Shape& sh,
+                               int32_t* ov, uint32_t cus, hipStream_t s);
+// Winners [F][k] from overlaps [F][C], one wave per frame (C <= 4096; else
+// hipErrorInvalidValue).
+hipError_t launch_topk_batch(const int32_t* ov, uint32_t F, const Shape& sh, int32_t* winners,
+                             hipStream_t s);
 
 }  // namespace htmsp

@@ -69,10 +69,25 @@ def q_to_float(q: np.ndarray) -> np.ndarray:
 
 
 def bernoulli_frames(g: np.random.Generator, frames: int, input_bits: int, p: float) -> np.ndarray:
-    """uint32[F][W]: every pixel on with probability p, independently."""
-    out = np.empty((frames, words_per_frame(input_bits)), dtype=np.uint32)
+    """uint32[F][W]: every pixel on with probability p, independently.  The
+    on-pixels are drawn as a Bernoulli process: gaps between successive
+    on-pixels are geometric(p), which is the same distribution as drawing
+    every pixel and far cheaper for sparse frames."""
+    n = int(input_bits)
+    out = np.zeros((frames, words_per_frame(n)), dtype=np.uint32)
+    if p <= 0.0:
+        return out
+    if p >= 1.0:
+        out[:] = pack_bits(np.ones(n, dtype=bool))
+        return out
+    chunk = int(n * p * 1.05) + 64
     for t in range(frames):
-        out[t] = pack_bits(g.random(input_bits) < p)
+        pos = np.cumsum(g.geometric(p, size=chunk)) - 1
+        while pos[-1] < n:
+            pos = np.concatenate([pos, pos[-1] + np.cumsum(g.geometric(p, size=chunk))])
+        bits = np.zeros(n, dtype=bool)
+        bits[pos[pos < n]] = True
+        out[t] = pack_bits(bits)
     return out
 
 
@@ -152,4 +167,15 @@ def workload_paper_scale(frames: int = 1000, columns: int = 1024, synapses: int 
     cfg = sp_config(960 * 540, columns, synapses, 4, 40)
     w = random_instance(seed, cfg, frames, density=0.05, shape=(960, 540), blobs=True)
     w.name = f"paper_960x540_{columns}c_{synapses}s"
+    return w
+
+
+def workload_batched_inference(frames: int = 4096, seed: int = 3) -> Workload:
+    """960x540 Bernoulli(0.05) frames through a frozen spatial pooler of 1024
+    columns x 256 synapses (min_overlap 4, 40 winners, threshold 0.5);
+    learning off."""
+    cfg = sp_config(960 * 540, 1024, 256, 4, 40)
+    w = random_instance(seed, cfg, frames, density=0.05)
+    w.learn = False
+    w.name = "infer_960x540_1024c_256s"
     return w

@@ -54,12 +54,12 @@ def algorithmic_bytes_infer(cfg: dict, F: int) -> int:
     return F * (frame_bytes(cfg) + 4 * C + 4 * k) + 8 * C * S
 
 
-def measured_traffic(profile: str, kernel_ms: float):
+def measured_traffic(profile: str, kernel: str, kernel_ms: float):
     """Counter bytes per launch from a committed summary, while the kernel
     source still matches the one the counters were taken from."""
     from paper_1608_01966_amd import profiling
     blk = profiling.read_block(os.path.join(PROFILES, profile))
-    if not blk or blk.get("source_sha256") != profiling.source_sha256():
+    if not blk or blk.get("source_sha256") != profiling.source_sha256(kernel):
         return None, None
     b = blk.get("hbm_bytes_per_launch")
     if b is None:
@@ -147,7 +147,7 @@ def bench_learn(args, torch, sp, synth):
     traffic, traffic_bytes = (None, None)
     if (C, S, F) == (1024, 256, 1000):
         traffic, traffic_bytes = measured_traffic("k_sp_persistent_960x540_1024c_256s.md",
-                                                  kernel_ms)
+                                                  "k_sp_persistent", kernel_ms)
 
     plain = None
     if args.plain_frames > 0:
@@ -218,7 +218,8 @@ def bench_infer(args, torch, sp, synth):
     fps = args.steps * F / wall_s
     abytes = algorithmic_bytes_infer(cfg, F)
     achieved = abytes / (call_ms * 1e-3) / 1e9
-    traffic, traffic_bytes = measured_traffic("k_infer_gather_960x540_1024c_256s.md", call_ms)
+    traffic, traffic_bytes = measured_traffic("k_infer_gather_960x540_1024c_256s.md", "k_infer_gather",
+                                              call_ms)
 
     # the same frames one launch sequence at a time, and through the
     # persistent sequential step with learning off
@@ -262,10 +263,175 @@ def bench_infer(args, torch, sp, synth):
     return line
 
 
+def bench_multi(args, torch, sp, synth):
+    ws = synth.workload_multi(instances=args.instances, frames=args.multi_frames)
+    stream = torch.cuda.current_stream()
+    pools = [sp.SpatialPooler(w.cfg, w.idx, w.perm) for w in ws]
+    perm0 = [p.perm.clone() for p in pools]
+    frames = [torch.from_numpy(np.ascontiguousarray(w.frames).view(np.int32)).cuda() for w in ws]
+    wins = [torch.empty((w.frames.shape[0], w.cfg["winners"]), dtype=torch.int32, device="cuda")
+            for w in ws]
+    handles = [p.handle for p in pools]
+    cfgs = [w.cfg for w in ws]
+    total = sum(w.frames.shape[0] for w in ws)
+
+    def reset():
+        for p, p0 in zip(pools, perm0):
+            p.perm.copy_(p0)
+
+    # Every step learns the same frames from the same initial states; the
+    # resets (one device copy per instance) stay inside the timed region.
+    def run(ev0=None, ev1=None):
+        reset()
+        if ev0 is not None:
+            ev0.record(stream)
+        sp.sp_step_many(handles, cfgs, frames, True, None, wins, stream)
+        if ev1 is not None:
+            ev1.record(stream)
+
+    for _ in range(args.warmup):
+        run()
+    pools[0].sync()
+    warm_clock(lambda: (run(), pools[0].sync()), args.warm_seconds)
+    wall_s, call_ms = timed(run, args.steps)
+    pools[0].sync()
+    ips = args.steps * total / wall_s
+
+    nsyn = sum(w.cfg["num_columns"] * w.cfg["synapses_per_column"] for w in ws)
+    abytes = 0
+    for w, wn in zip(ws, wins):
+        cfg = dict(w.cfg)
+        F = w.frames.shape[0]
+        nw = int((wn.cpu().numpy() >= 0).sum())
+        S = cfg["synapses_per_column"]
+        abytes += F * (frame_bytes(cfg) + 8 * cfg["num_columns"] * S + 4 * cfg["winners"])
+        abytes += 12 * S * nw
+    achieved = abytes / (call_ms * 1e-3) / 1e9
+    traffic, traffic_bytes = measured_traffic("k_sp_many_64_instances.md", "k_sp_many", call_ms)
+
+    # the same instances stepped one after another by the single-instance path
+    reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for p, w, f, wn in zip(pools, ws, frames, wins):
+        sp.sp_step(p.handle, w.cfg, f, True, None, wn, stream)
+    torch.cuda.synchronize()
+    seq = total / (time.perf_counter() - t0)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        n, dt = 2, 0.0
+        while True:
+            t0 = time.perf_counter()
+            for w in ws:
+                oracle.run(w.cfg, w.idx, w.perm, w.frames[:n], learn=True, want_overlaps=False)
+            dt = time.perf_counter() - t0
+            if dt > args.cpu_budget / 3 or n >= args.multi_frames:
+                break
+            n = min(2 * n, args.multi_frames)
+        cpu = {"value": n * len(ws) / dt, "unit": "instance-frames/s", "cores": 1,
+               "kind": "oracle", "sample": f"first {n} frames of each of the {len(ws)} "
+                                           f"instances from the same states, {dt:.2f} s "
+                                           f"single-threaded"}
+    line = {
+        "metric": "SP instance-frames/s, 64 uneven instances, learning on",
+        "value": ips, "unit": "instance-frames/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall_s / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"{len(ws)} independent poolers (columns 256-4096, synapses "
+                               f"32-512, inputs 64x64-960x540 at 2-10% density), "
+                               f"{args.multi_frames} learning frames each per step",
+                   "instances": len(ws), "frames_per_instance": args.multi_frames,
+                   "synapses_total": nsyn, "path": "many"},
+        "synapse_updates_per_s": args.steps * sum(
+            w.frames.shape[0] * w.cfg["num_columns"] * w.cfg["synapses_per_column"]
+            for w in ws) / wall_s,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_sp_many", "kernel_ms_per_launch": call_ms,
+                     "algorithmic_bytes_per_launch": abytes,
+                     "counter_bytes_per_launch": traffic_bytes},
+        "sequential_single_instance_launches_instance_frames_per_s": seq,
+        "cpu_baseline": cpu,
+    }
+    for p in pools:
+        p.close()
+    return line
+
+
+def bench_serve(args, torch, sp, synth):
+    from paper_1608_01966_amd import serve
+    P = args.pool_frames
+    frames = synth.blob_frames(synth.rng(5, 2), P, 960, 540, 0.05)
+    pool = torch.from_numpy(frames.view(np.int32)).cuda()
+    specs = serve.make_streams(args.streams, fps=args.fps, window=args.window, pool_frames=P)
+    probe = serve.GpuBackend(pool, keep_outputs=False)
+    total_bytes = sum(probe.stream_bytes(s) for s in specs)
+    budget = int(total_bytes * args.budget_frac)
+    offered = sum(len(s.arrivals) for s in specs)
+
+    def serve_once(scale: float):
+        sc = [serve.StreamSpec(s.sid, s.cfg, s.idx, s.perm, s.arrivals / scale, s.frame_ids)
+              for s in specs]
+        be = serve.GpuBackend(pool, keep_outputs=False)
+        srv = serve.Server(be, sc, budget_bytes=budget, max_frames_per_tick=args.max_frames_tick)
+        t0 = time.perf_counter()
+        srv.run()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        lat = srv.latencies(skip_before=1.0 / scale)
+        last = max(t for st in srv.streams for _, t in st.completions)
+        return srv, wall, lat, offered / last
+
+    # real time: every stream at its own rate
+    srv, wall, lat, fps_rt = serve_once(1.0)
+    rt = {"offered_frames_per_s": offered / args.window, "frames_per_s": fps_rt,
+          "p50_ms": float(np.percentile(lat, 50) * 1e3),
+          "p99_ms": float(np.percentile(lat, 99) * 1e3), "max_ms": float(lat.max() * 1e3),
+          "batches": len(srv.batch_sizes), "mean_batch_frames": float(np.mean(srv.batch_sizes)),
+          "peak_resident_bytes": srv.peak_used, "budget_bytes": budget,
+          "max_admission_wait_ms": float(max(srv.admit_waits) * 1e3)}
+    # saturation: the same arrivals compressed until throughput stops growing
+    sat = []
+    for scale in args.saturation_scales:
+        s2, wall2, lat2, fps2 = serve_once(scale)
+        sat.append({"arrival_scale": scale, "frames_per_s": fps2,
+                    "p50_ms": float(np.percentile(lat2, 50) * 1e3),
+                    "p99_ms": float(np.percentile(lat2, 99) * 1e3),
+                    "mean_batch_frames": float(np.mean(s2.batch_sizes))})
+    best = max(sat, key=lambda r: r["frames_per_s"]) if sat else None
+    line = {
+        "metric": "SP serve: p99 frame latency at 30 fps per stream, and saturated frames/s",
+        "value": rt["p99_ms"], "unit": "ms", "n_gpus": 1, "steps": 1 + len(sat),
+        "warmup": 0, "ms_per_step": wall * 1e3, "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"{args.streams} streams over {args.window:.0f} s, 960x540 "
+                               f"blob frames (~5% on) at {args.fps:g} fps Poisson per stream, "
+                               f"poolers 256-4096 columns x 32-512 synapses, learning on, "
+                               f"admission budget {args.budget_frac:.0%} of all state",
+                   "streams": args.streams, "frames_offered": offered, "path": "serve"},
+        "real_time": rt,
+        "saturation": sat,
+        "saturated_frames_per_s": best["frames_per_s"] if best else None,
+    }
+    return line
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["learn", "infer"], default="learn")
+    ap.add_argument("--workload", choices=["learn", "infer", "multi", "serve"], default="learn")
+    ap.add_argument("--streams", type=int, default=256)
+    ap.add_argument("--fps", type=float, default=30.0)
+    ap.add_argument("--window", type=float, default=10.0)
+    ap.add_argument("--pool-frames", type=int, default=512)
+    ap.add_argument("--budget-frac", type=float, default=1.0)
+    ap.add_argument("--max-frames-tick", type=int, default=8)
+    ap.add_argument("--saturation-scales", type=float, nargs="*", default=[40.0, 160.0])
+    ap.add_argument("--instances", type=int, default=64)
+    ap.add_argument("--multi-frames", type=int, default=500)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--warm-seconds", type=float, default=1.0,
@@ -301,7 +467,8 @@ def main() -> int:
         torch.cuda.synchronize()
         del src, dst
 
-    fn = bench_learn if args.workload == "learn" else bench_infer
+    fn = {"learn": bench_learn, "infer": bench_infer, "multi": bench_multi,
+          "serve": bench_serve}[args.workload]
     line = fn(args, torch, sp, synth)
     print(json.dumps(line), flush=True)
     return 0

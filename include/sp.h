@@ -145,6 +145,21 @@ int sp_step_plain(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames,
 int sp_infer(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames, int mode,
              int32_t* overlaps_dev, int32_t* winners_dev, void* stream);
 
+/* Steps n independent handles together (each handle as by sp_step: its
+ * frames in order, overlap, inhibition and, when learn != 0, learning) in one
+ * persistent launch whose workgroups serve tiles of every instance and one
+ * top-k task per instance, synapse state streamed from device memory every
+ * step.  Arrays have n entries: frames_dev[i] holds num_frames[i] frames of
+ * handle i (0 = skip it), winners_dev[i] is [num_frames[i]][k_i],
+ * overlaps_dev may be NULL or hold NULL entries.  Handles must be distinct,
+ * on one device, with at most 4096 columns each.  Results equal stepping each
+ * handle alone.  A device-side failure is reported by sp_sync on hs[0].
+ * Calls are serialised by the library; one call's launch must not overlap
+ * another call's on a different stream. */
+int sp_step_many(sp_handle* const* hs, uint32_t n, const uint32_t* const* frames_dev,
+                 const uint32_t* num_frames, int learn, int32_t* const* overlaps_dev,
+                 int32_t* const* winners_dev, void* stream);
+
 /* 1 if sp_step runs this handle's shape as one persistent launch, 0 if it
  * runs the plain path, negative on a bad handle. */
 int sp_step_is_persistent(const sp_handle* h);

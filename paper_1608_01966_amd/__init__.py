@@ -26,7 +26,8 @@ from ._native import (SP_EBROKEN, SP_EDEVICE, SP_EINVAL, SP_ENOMEM, SP_INFER_GAT
 __all__ = [
     "SpError", "SpatialPooler", "synth", "sp_config_check", "sp_frame_words",
     "sp_workspace_bytes", "sp_check_state_host", "sp_create", "sp_check_state", "sp_step",
-    "sp_step_plain", "sp_infer", "sp_step_is_persistent", "sp_sync", "sp_destroy",
+    "sp_step_plain", "sp_infer", "sp_step_many", "sp_step_is_persistent", "sp_sync",
+    "sp_destroy",
     "sp_last_error", "SP_OK", "SP_EINVAL", "SP_ENOMEM", "SP_EDEVICE", "SP_EBROKEN",
     "SP_INFER_GATHER",
 ]
@@ -151,6 +152,30 @@ def sp_infer(h: int, cfg, frames, mode: int, overlaps, winners, stream=None) -> 
            "sp_infer")
 
 
+def sp_step_many(handles, cfgs, frames, learn: bool, overlaps, winners, stream=None) -> None:
+    """Steps several handles in one launch.  frames[i] is an int32 GPU tensor
+    [F_i][W_i] (F_i may be 0); overlaps[i] may be None (or overlaps None);
+    winners[i] is [F_i][k_i]."""
+    import torch
+    n = len(handles)
+    H = (ctypes.c_void_p * n)(*[ctypes.c_void_p(h) for h in handles])
+    FR = (ctypes.c_void_p * n)()
+    NF = (ctypes.c_uint32 * n)()
+    OV = (ctypes.c_void_p * n)()
+    WN = (ctypes.c_void_p * n)()
+    for i in range(n):
+        c = _cfg(cfgs[i])
+        F = int(frames[i].shape[0])
+        W = (c.input_bits + 31) // 32
+        NF[i] = F
+        FR[i] = _dev(frames[i], torch.int32, (F, W), f"frames[{i}]")
+        ov = overlaps[i] if overlaps is not None else None
+        OV[i] = _dev(ov, torch.int32, (F, c.num_columns), f"overlaps[{i}]")
+        WN[i] = _dev(winners[i], torch.int32, (F, c.winners), f"winners[{i}]")
+    _check(lib().sp_step_many(H, n, FR, NF, int(bool(learn)), OV, WN, _stream(stream)),
+           "sp_step_many")
+
+
 def sp_step_is_persistent(h: int) -> bool:
     return bool(_check(lib().sp_step_is_persistent(ctypes.c_void_p(h)), "sp_step_is_persistent"))
 
@@ -180,6 +205,10 @@ class SpatialPooler:
             perm = torch.from_numpy(np.ascontiguousarray(perm, dtype=np.float32))
         self.idx = idx.to(device=device, dtype=torch.int32).contiguous()
         self.perm = perm.to(device=device, dtype=torch.float32).contiguous()
+        if stream is not None:
+            # the copies above ran on the current stream; sp_create checks
+            # the state on `stream`
+            torch.cuda.current_stream(self.idx.device).synchronize()
         self.handle = sp_create(self.cfg, self.idx, self.perm, stream)
 
     @property

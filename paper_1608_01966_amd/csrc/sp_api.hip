@@ -5,9 +5,13 @@
 #include <stdarg.h>
 #include <stdio.h>
 
+#include <string.h>
+
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "sp.h"
 #include "sp_internal.h"
@@ -26,6 +30,9 @@ struct sp_handle {
   uint32_t* err;       // [1] (padded)
   uint32_t* check;     // [4]
   int32_t* ov_scratch; // [C]
+  uint32_t* many_ovx;  // [C] tagged overlaps of the many-instance step
+  uint64_t* many_dec;  // decision word of the many-instance step
+  uint32_t many_steps; // steps this handle has taken through sp_step_many
   uint64_t xchg_frames;
   bool persistent;
   uint32_t grid, replicas;
@@ -72,7 +79,7 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Workspace layout, each part 256-byte aligned.
 struct WsLayout {
-  size_t xchg, err, check, ov, total;
+  size_t xchg, err, check, ov, many_ovx, many_dec, total;
 };
 
 WsLayout ws_layout(const sp_config& c) {
@@ -84,7 +91,10 @@ WsLayout ws_layout(const sp_config& c) {
                    256);
   l.check = align_up(l.err + sizeof(uint32_t), 256);
   l.ov = align_up(l.check + 4 * sizeof(uint32_t), 256);
-  l.total = align_up(l.ov + sizeof(int32_t) * (size_t)c.num_columns, 256);
+  l.many_ovx = align_up(l.ov + sizeof(int32_t) * (size_t)c.num_columns, 256);
+  // read in pairs of entries by 256-column words
+  l.many_dec = align_up(l.many_ovx + sizeof(uint32_t) * align_up(c.num_columns, 256), 256);
+  l.total = align_up(l.many_dec + sizeof(uint64_t), 256);
   return l;
 }
 
@@ -211,6 +221,58 @@ int run_check_state(sp_handle* h, hipStream_t s) {
   return SP_OK;
 }
 
+// Descriptor staging for sp_step_many: two slots of pinned host memory and
+// device memory per device, so that a call only waits for the launch two
+// calls back before it rewrites a slot.
+struct ManySlot {
+  void* host = nullptr;
+  void* dev = nullptr;
+  size_t cap = 0;
+  hipEvent_t done = nullptr;
+};
+
+struct ManyCtx {
+  int device = -1;
+  ManySlot slot[2];
+  int next = 0;
+};
+
+std::mutex g_many_mu;
+ManyCtx g_many[16];
+
+int many_slot(int device, size_t bytes, ManySlot** out) {
+  if (device < 0 || device >= 16) return fail(SP_EDEVICE, "device %d out of range", device);
+  ManyCtx& ctx = g_many[device];
+  ctx.device = device;
+  ManySlot& sl = ctx.slot[ctx.next];
+  ctx.next ^= 1;
+  hipError_t e = hipSuccess;
+  if (sl.done) {
+    e = hipEventSynchronize(sl.done);
+    if (e != hipSuccess) return hip_fail(e, "many-instance staging");
+  } else {
+    e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "many-instance event");
+  }
+  if (sl.cap < bytes) {
+    if (sl.host) (void)hipHostFree(sl.host);
+    if (sl.dev) (void)hipFree(sl.dev);
+    sl.host = sl.dev = nullptr;
+    sl.cap = 0;
+    const size_t cap = std::max<size_t>(bytes, 1 << 16) * 2;
+    e = hipHostMalloc(&sl.host, cap, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMalloc(&sl.dev, cap);
+    if (e != hipSuccess) {
+      if (sl.host) (void)hipHostFree(sl.host);
+      sl.host = sl.dev = nullptr;
+      return fail(SP_ENOMEM, "many-instance staging allocation (%zu bytes)", cap);
+    }
+    sl.cap = cap;
+  }
+  *out = &sl;
+  return SP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -278,6 +340,8 @@ int sp_create(const sp_config* cfg, uint32_t* idx_dev, float* perm_dev, void* st
   h->err = reinterpret_cast<uint32_t*>(base + l.err);
   h->check = reinterpret_cast<uint32_t*>(base + l.check);
   h->ov_scratch = reinterpret_cast<int32_t*>(base + l.ov);
+  h->many_ovx = reinterpret_cast<uint32_t*>(base + l.many_ovx);
+  h->many_dec = reinterpret_cast<uint64_t*>(base + l.many_dec);
   e = hipMemsetAsync(h->ws, 0, l.total, s);
   if (e != hipSuccess) {
     (void)hipFree(h->ws);
@@ -420,6 +484,110 @@ int sp_infer(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames, int 
   else
     e = htmsp::launch_topk_plain(ov, winners_dev, sh, s, num_frames);
   if (e != hipSuccess) return hip_fail(e, "inference top-k launch");
+  return ok();
+}
+
+int sp_step_many(sp_handle* const* hs, uint32_t n, const uint32_t* const* frames_dev,
+                 const uint32_t* num_frames, int learn, int32_t* const* overlaps_dev,
+                 int32_t* const* winners_dev, void* stream) {
+  if (n == 0) return ok();
+  if (!hs || !frames_dev || !num_frames || !winners_dev)
+    return fail(SP_EINVAL, "handles, frames, num_frames and winners arrays are required");
+  int dev = -1;
+  uint32_t Fmax = 0;
+  size_t ntiles = 0, nact = 0;
+  for (uint32_t i = 0; i < n; ++i) {
+    const sp_handle* h = hs[i];
+    int rc = check_step_args(h, frames_dev[i], num_frames[i],
+                             overlaps_dev ? overlaps_dev[i] : nullptr, winners_dev[i]);
+    if (rc) return fail(rc, "instance %u: %s", i, g_err.c_str());
+    if (dev < 0) dev = h->device;
+    if (h->device != dev) return fail(SP_EINVAL, "instance %u is on another device", i);
+    if (h->sh.C > 4 * 64 * htmsp::kManyNV)
+      return fail(SP_EINVAL, "instance %u has %u columns; stepping many instances holds at most %u",
+                  i, h->sh.C, 4 * 64 * htmsp::kManyNV);
+    for (uint32_t j = 0; j < i; ++j)
+      if (hs[j] == h) return fail(SP_EINVAL, "instance %u repeats instance %u", i, j);
+    if (num_frames[i] == 0) continue;
+    Fmax = std::max(Fmax, num_frames[i]);
+    const uint32_t ct = htmsp::many_tile_columns(h->sh.S);
+    ntiles += (h->sh.C + ct - 1) / ct;
+    ++nact;
+  }
+  if (nact == 0) return ok();
+  DeviceScope ds(dev);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int maxb = htmsp::many_max_blocks(dev);
+  if (maxb <= 0) return fail(SP_EDEVICE, "cannot size the many-instance launch");
+  const uint32_t ntasks = (uint32_t)(ntiles + nact);
+  const uint32_t grid = std::min<uint32_t>(ntasks, (uint32_t)maxb);
+
+  // Tasks: tiles dealt round-robin over the blocks, top-k tasks from the
+  // last block backwards; in each block tiles come before top-k tasks.
+  std::vector<std::vector<htmsp::ManyTask>> per(grid);
+  std::vector<htmsp::ManyInst> insts;
+  insts.reserve(nact);
+  uint32_t next_tile = 0, next_topk = 0;
+  for (uint32_t i = 0; i < n; ++i) {
+    sp_handle* h = hs[i];
+    if (num_frames[i] == 0) continue;
+    const uint32_t id = (uint32_t)insts.size();
+    htmsp::ManyInst in = {};
+    in.idx = h->idx;
+    in.perm = h->perm;
+    in.frames = frames_dev[i];
+    in.ov_out = overlaps_dev ? overlaps_dev[i] : nullptr;
+    in.win_out = winners_dev[i];
+    in.ovx = h->many_ovx;
+    in.dec = h->many_dec;
+    in.sh = h->sh;
+    in.F = num_frames[i];
+    in.step_base = h->many_steps;
+    in.guess = 1 + h->sh.S / 16;
+    insts.push_back(in);
+    const uint32_t ct = htmsp::many_tile_columns(h->sh.S);
+    for (uint32_t c0 = 0; c0 < h->sh.C; c0 += ct)
+      per[next_tile++ % grid].push_back({id, 0u, c0, std::min(h->sh.C, c0 + ct)});
+  }
+  for (uint32_t id = 0; id < insts.size(); ++id)
+    per[grid - 1 - (next_topk++ % grid)].push_back({id, 1u, 0u, 0u});
+
+  const size_t b_insts = align_up(sizeof(htmsp::ManyInst) * insts.size(), 256);
+  const size_t b_tasks = align_up(sizeof(htmsp::ManyTask) * ntasks, 256);
+  const size_t b_off = sizeof(uint32_t) * (grid + 1);
+  std::lock_guard<std::mutex> lock(g_many_mu);
+  ManySlot* sl = nullptr;
+  int rc = many_slot(dev, b_insts + b_tasks + b_off, &sl);
+  if (rc) return rc;
+  char* hb = static_cast<char*>(sl->host);
+  char* db = static_cast<char*>(sl->dev);
+  memcpy(hb, insts.data(), sizeof(htmsp::ManyInst) * insts.size());
+  htmsp::ManyTask* ht = reinterpret_cast<htmsp::ManyTask*>(hb + b_insts);
+  uint32_t* hoff = reinterpret_cast<uint32_t*>(hb + b_insts + b_tasks);
+  uint32_t k = 0;
+  for (uint32_t b = 0; b < grid; ++b) {
+    hoff[b] = k;
+    for (const auto& t : per[b]) ht[k++] = t;
+  }
+  hoff[grid] = k;
+  hipError_t e = hipMemcpyAsync(db, hb, b_insts + b_tasks + b_off, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "many-instance descriptors");
+  htmsp::ManyArgs a = {};
+  a.insts = reinterpret_cast<htmsp::ManyInst*>(db);
+  a.tasks = reinterpret_cast<const htmsp::ManyTask*>(db + b_insts);
+  a.task_off = reinterpret_cast<const uint32_t*>(db + b_insts + b_tasks);
+  a.err = hs[0]->err;
+  a.Fmax = Fmax;
+  a.learn = learn ? 1u : 0u;
+  a.spin_limit = kSpinLimit;
+  e = htmsp::launch_many(a, grid, s);
+  if (e == hipSuccess) e = hipEventRecord(sl->done, s);
+  if (e != hipSuccess) return hip_fail(e, "many-instance launch");
+  for (uint32_t i = 0; i < n; ++i) {
+    if (num_frames[i] == 0) continue;
+    hs[i]->many_steps += num_frames[i];
+    if (learn) ++hs[i]->state_version;
+  }
   return ok();
 }
 

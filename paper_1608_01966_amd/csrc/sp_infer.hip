@@ -21,8 +21,15 @@ using namespace dev;
 
 constexpr uint32_t kInferThreads = 256;
 
+// List entry for input pixel p: its frame word in the high bits, its bit in
+// the low five, so one shift gives the word and a bit-field extract (which
+// reads only the low five bits of its offset) gives the bit.
+__device__ __forceinline__ uint32_t list_entry(uint32_t p) { return ((p >> 5) << 7) | (p & 31u); }
+__device__ __forceinline__ uint32_t entry_word(uint32_t e) { return e >> 7; }
+
 // Column c's connected inputs, slot-major: list[i * C + c] for i < cnt[c];
-// slots from cnt[c] to S - 1 hold `pad`, a pixel whose word is always 0.
+// slots from cnt[c] to S - 1 hold `pad`, the entry of a word that is always
+// zero (one past the frame).
 __global__ __launch_bounds__(256) void k_infer_prep(const uint32_t* __restrict__ idx,
                                                     const float* __restrict__ perm, Shape sh,
                                                     uint32_t pad, uint32_t* __restrict__ list,
@@ -33,7 +40,8 @@ __global__ __launch_bounds__(256) void k_infer_prep(const uint32_t* __restrict__
   uint32_t n = 0;
   for (uint32_t s = 0; s < sh.S; ++s) {
     const size_t off = (size_t)c * sh.S + s;
-    if (perm_to_q(perm[off]) >= sh.theta) list[(size_t)n++ * sh.C + c] = min(idx[off], sh.N - 1);
+    if (perm_to_q(perm[off]) >= sh.theta)
+      list[(size_t)n++ * sh.C + c] = list_entry(min(idx[off], sh.N - 1));
   }
   cnt[c] = n;
   for (uint32_t i = n; i < sh.S; ++i) list[(size_t)i * sh.C + c] = pad;
@@ -57,7 +65,7 @@ __global__ __launch_bounds__(kInferThreads) void k_infer_gather(
   if (fg >= groups) return;
   const uint32_t c = cb * kInferThreads + threadIdx.x;
   const bool col_ok = c < sh.C;
-  const uint32_t pad = sh.W * 32;
+  const uint32_t pad = sh.W << 7;
 
   uint32_t lst[MAXN];
 #pragma unroll
@@ -85,16 +93,20 @@ __global__ __launch_bounds__(kInferThreads) void k_infer_gather(
       if (threadIdx.x == 0) fr[sh.W] = 0u;
       __syncthreads();
     }
+    // Keep one register per list entry: the empty asm stops the compiler
+    // from hoisting each entry's word address out of the frame loop.
+#pragma unroll
+    for (int i = 0; i < MAXN; ++i) asm volatile("" : "+v"(lst[i]));
     uint32_t acc = 0;
 #pragma unroll
     for (int i0 = 0; i0 < MAXN; i0 += 16) {
       if ((uint32_t)i0 < n) {
 #pragma unroll
         for (int i = i0; i < i0 + 16; ++i) {
-          const uint32_t p = lst[i];
-          const uint32_t wi = p >> 5;
+          const uint32_t e = lst[i];
+          const uint32_t wi = entry_word(e);
           const uint32_t word = LDS ? fr[wi] : (wi < sh.W ? frame[wi] : 0u);
-          acc += input_bit(word, p);
+          acc += __builtin_amdgcn_ubfe(word, e, 1);
         }
       }
     }
@@ -191,7 +203,7 @@ hipError_t launch_infer_prep(const uint32_t* idx, const float* perm, const Shape
   hipError_t e = hipMemsetAsync(maxcnt, 0, sizeof(uint32_t), s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_infer_prep, dim3((sh.C + 255) / 256), dim3(256), 0, s, idx, perm, sh,
-                     sh.W * 32, list, cnt, maxcnt);
+                     sh.W << 7, list, cnt, maxcnt);
   return hipGetLastError();
 }
 

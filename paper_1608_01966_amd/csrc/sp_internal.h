@@ -78,4 +78,40 @@ hipError_t launch_infer_gather(uint32_t maxn, const uint32_t* frames, uint32_t F
 hipError_t launch_topk_batch(const int32_t* ov, uint32_t F, const Shape& sh, int32_t* winners,
                              hipStream_t s);
 
+// Many instances in one persistent launch (sp_many.hip).
+constexpr uint32_t kManyNV = 16;          // top-k words per lane: C <= 4096
+constexpr uint32_t kTileSynapses = 8192;  // synapses per tile task (at most)
+constexpr uint32_t kTileColumns = 1024;   // columns per tile task (at most)
+constexpr uint32_t kManyThreads = 256;
+
+struct ManyInst {
+  const uint32_t* idx;
+  float* perm;
+  const uint32_t* frames;  // [F][W]
+  int32_t* ov_out;         // [F][C] or null
+  int32_t* win_out;        // [F][k]
+  uint32_t* ovx;           // [C] tagged overlaps
+  uint64_t* dec;           // decision word
+  Shape sh;
+  uint32_t F, step_base, guess, pad;
+};
+
+struct ManyTask {
+  uint32_t inst, kind, c0, c1;  // kind 0: tile [c0, c1); kind 1: top-k
+};
+
+struct ManyArgs {
+  ManyInst* insts;
+  const ManyTask* tasks;
+  const uint32_t* task_off;  // [grid + 1]: tasks of block b are [task_off[b], task_off[b+1])
+  uint32_t* err;
+  uint32_t Fmax, learn, spin_limit, pad;
+};
+
+// Columns of one tile task for S synapses per column.
+uint32_t many_tile_columns(uint32_t S);
+// Co-resident blocks of the many-instance kernel on `device` (0 on error).
+int many_max_blocks(int device);
+hipError_t launch_many(const ManyArgs& a, uint32_t grid, hipStream_t s);
+
 }  // namespace htmsp

@@ -25,15 +25,20 @@ import os
 import re
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = [os.path.join(PKG, "csrc", f) for f in ("sp_kernels.hip", "sp_internal.h")]
+# the source files each profiled kernel is compiled from
+KERNEL_SOURCES = {
+    "k_sp_persistent": ("sp_kernels.hip", "sp_device.h", "sp_internal.h"),
+    "k_infer_gather": ("sp_infer.hip", "sp_device.h", "sp_internal.h"),
+    "k_sp_many": ("sp_many.hip", "sp_device.h", "sp_internal.h"),
+}
 COPY_KERNEL = "vectorized_elementwise_kernel"
 
 
-def source_sha256() -> str:
+def source_sha256(kernel: str) -> str:
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
-        with open(p, "rb") as f:
-            h.update(f.read())
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(PKG, "csrc", f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()
 
 
@@ -77,7 +82,8 @@ def summarize(args) -> str:
                    f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
                    f"{float(r['Percentage']):.1f}% |")
     out.append("")
-    block = {"kernel": args.kernel, "workload": args.workload, "source_sha256": source_sha256()}
+    block = {"kernel": args.kernel, "workload": args.workload,
+             "source_sha256": source_sha256(args.kernel)}
     avg = [float(r["AverageNs"]) for r in stats if r["Name"] == args.kernel]
     if avg:
         block["trace_avg_ms"] = avg[0] / 1e6

@@ -81,13 +81,15 @@ def bernoulli_frames(g: np.random.Generator, frames: int, input_bits: int, p: fl
         out[:] = pack_bits(np.ones(n, dtype=bool))
         return out
     chunk = int(n * p * 1.05) + 64
+    W = words_per_frame(n)
     for t in range(frames):
         pos = np.cumsum(g.geometric(p, size=chunk)) - 1
         while pos[-1] < n:
             pos = np.concatenate([pos, pos[-1] + np.cumsum(g.geometric(p, size=chunk))])
-        bits = np.zeros(n, dtype=bool)
-        bits[pos[pos < n]] = True
-        out[t] = pack_bits(bits)
+        pos = pos[pos < n]
+        # distinct positions: summing their bit values is OR-ing them
+        out[t] = np.bincount(pos >> 5, weights=np.left_shift(1, pos & 31).astype(np.float64),
+                             minlength=W).astype(np.uint32)
     return out
 
 
@@ -179,3 +181,26 @@ def workload_batched_inference(frames: int = 4096, seed: int = 3) -> Workload:
     w.learn = False
     w.name = "infer_960x540_1024c_256s"
     return w
+
+
+INPUT_SHAPES = [(64, 64), (128, 128), (240, 134), (480, 270), (960, 540)]
+
+
+def workload_multi(instances: int = 64, frames: int = 500, seed: int = 4) -> list:
+    """Independent spatial poolers of uneven size: columns from
+    {256, ..., 4096}, synapses from {32, ..., 512}, inputs from 64x64 to
+    960x540 at a density drawn uniformly in [0.02, 0.10] (Bernoulli pixels);
+    min_overlap 4, 10 winners per 256 columns; learning on."""
+    g = rng(seed, 0)
+    out = []
+    for i in range(instances):
+        C = int(g.choice([256, 512, 1024, 2048, 4096]))
+        S = int(g.choice([32, 64, 128, 256, 512]))
+        wd, ht = INPUT_SHAPES[int(g.integers(0, len(INPUT_SHAPES)))]
+        d = float(g.uniform(0.02, 0.10))
+        cfg = sp_config(wd * ht, C, S, 4, 10 * C // 256)
+        w = random_instance(seed * 1000 + i, cfg, frames, density=d)
+        w.name = f"multi_{i}_{wd}x{ht}_{C}c_{S}s"
+        w.meta = {"shape": (wd, ht), "density": d}
+        out.append(w)
+    return out

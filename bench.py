@@ -218,7 +218,8 @@ def bench_infer(args, torch, sp, synth):
     fps = args.steps * F / wall_s
     abytes = algorithmic_bytes_infer(cfg, F)
     achieved = abytes / (call_ms * 1e-3) / 1e9
-    traffic, traffic_bytes = measured_traffic("k_infer_gather_960x540_1024c_256s.md", "k_infer_gather",
+    traffic, traffic_bytes = measured_traffic("k_infer_gather_960x540_1024c_256s.md",
+                                              "k_infer_gather+k_topk_batch",
                                               call_ms)
 
     # the same frames one launch sequence at a time, and through the

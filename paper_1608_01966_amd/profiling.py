@@ -29,14 +29,24 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = {
     "k_sp_persistent": ("sp_kernels.hip", "sp_device.h", "sp_internal.h"),
     "k_infer_gather": ("sp_infer.hip", "sp_device.h", "sp_internal.h"),
+    "k_topk_batch": ("sp_infer.hip", "sp_device.h", "sp_internal.h"),
     "k_sp_many": ("sp_many.hip", "sp_device.h", "sp_internal.h"),
 }
 COPY_KERNEL = "vectorized_elementwise_kernel"
 
 
-def source_sha256(kernel: str) -> str:
+def kernels_of(spec: str) -> list[str]:
+    """'a+b' -> ['a', 'b']: a profiled unit may be several kernels launched
+    back to back by one library call."""
+    return [k for k in spec.split("+") if k]
+
+
+def source_sha256(spec: str) -> str:
+    files = []
+    for k in kernels_of(spec):
+        files += [f for f in KERNEL_SOURCES[k] if f not in files]
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES[kernel]:
+    for f in files:
         with open(os.path.join(PKG, "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -65,9 +75,14 @@ def calibrated(pmc_dir: str, name: str, kernel: str, copy_bytes: int):
     copy = [float(r["Counter_Value"]) for r in rows if r["Kernel_Name"].startswith(COPY_KERNEL)]
     # the copy is the elementwise kernel that moves the most data
     factor = copy_bytes / 1024.0 / max(copy) if copy and max(copy) > 0 else None
-    ours = [float(r["Counter_Value"]) for r in rows if r["Kernel_Name"] == kernel]
-    kib = sum(ours) / len(ours) if ours else None
-    return kib, factor, len(ours)
+    kib, n = 0.0, None
+    for k in kernels_of(kernel):
+        ours = [float(r["Counter_Value"]) for r in rows if r["Kernel_Name"] == k]
+        if not ours:
+            return None, factor, 0
+        kib += sum(ours) / len(ours)
+        n = len(ours) if n is None else min(n, len(ours))
+    return kib, factor, n
 
 
 def summarize(args) -> str:
@@ -84,9 +99,10 @@ def summarize(args) -> str:
     out.append("")
     block = {"kernel": args.kernel, "workload": args.workload,
              "source_sha256": source_sha256(args.kernel)}
-    avg = [float(r["AverageNs"]) for r in stats if r["Name"] == args.kernel]
-    if avg:
-        block["trace_avg_ms"] = avg[0] / 1e6
+    avg = [float(r["AverageNs"]) for k in kernels_of(args.kernel) for r in stats
+           if r["Name"] == k]
+    if len(avg) == len(kernels_of(args.kernel)):
+        block["trace_avg_ms"] = sum(avg) / 1e6
     copy_bytes = args.copy_mb * (1 << 20)
     if args.fetch and args.write:
         fk, ff, nf = calibrated(args.fetch, "FETCH_SIZE", args.kernel, copy_bytes)
@@ -123,7 +139,7 @@ def main():
     s.add_argument("--trace", required=True)
     s.add_argument("--fetch")
     s.add_argument("--write")
-    s.add_argument("--kernel", required=True)
+    s.add_argument("--kernel", required=True, help="kernel name, or names joined by '+'")
     s.add_argument("--workload", required=True)
     s.add_argument("--command", required=True)
     s.add_argument("--copy-mb", type=int, default=256)

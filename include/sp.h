@@ -160,6 +160,16 @@ int sp_step_many(sp_handle* const* hs, uint32_t n, const uint32_t* const* frames
                  const uint32_t* num_frames, int learn, int32_t* const* overlaps_dev,
                  int32_t* const* winners_dev, void* stream);
 
+/* Per-stream SDR histogram (Section 2: the pooler output of every frame of a
+ * video is accumulated into a histogram, the video's feature vector).
+ * hist_dev: caller-owned uint32 [num_columns] device buffer, or NULL to stop.
+ * From then on every sp_step, sp_step_plain, sp_infer and sp_step_many of
+ * this handle adds, for each frame, 1 to hist_dev[c] for each winner c, on
+ * the call's stream after its winners are written.  The library never clears
+ * it; the buffer must outlive its use.  SP_EINVAL on a bad handle or a
+ * misaligned pointer. */
+int sp_set_histogram(sp_handle* h, uint32_t* hist_dev);
+
 /* 1 if sp_step runs this handle's shape as one persistent launch, 0 if it
  * runs the plain path, negative on a bad handle. */
 int sp_step_is_persistent(const sp_handle* h);

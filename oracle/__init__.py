@@ -65,6 +65,8 @@ def _load():
         lib.spo_learn.restype = None
         lib.spo_run.argtypes = [ctypes.POINTER(_Cfg), P, P, P, ctypes.c_uint32, ctypes.c_int, P, P]
         lib.spo_run.restype = ctypes.c_int
+        lib.spo_histogram.argtypes = [P, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, P]
+        lib.spo_histogram.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -141,3 +143,15 @@ def run(cfg: dict, idx: np.ndarray, perm: np.ndarray, frames: np.ndarray, learn:
     if rc != 0:
         raise ValueError("oracle rejected its arguments")
     return ov, win, perm
+
+
+def histogram(winners: np.ndarray, num_columns: int, hist: np.ndarray | None = None) -> np.ndarray:
+    """Adds every frame's winners (int32 [F][k], -1 padded) to a per-column
+    count (uint32 [C], zeros when not given) and returns it."""
+    w = np.ascontiguousarray(winners, dtype=np.int32)
+    F, k = (w.shape[0], w.shape[1]) if w.ndim == 2 else (0, 1)
+    h = (np.zeros(num_columns, dtype=np.uint32) if hist is None
+         else np.array(hist, dtype=np.uint32, copy=True))
+    if _load().spo_histogram(_ptr(w), F, k, int(num_columns), _ptr(h)) != 0:
+        raise ValueError("winner index out of range")
+    return h

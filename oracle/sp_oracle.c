@@ -121,3 +121,16 @@ int spo_run(const spo_config* cfg, const uint32_t* idx, double* perm,
   free(active);
   return 0;
 }
+
+int spo_histogram(const int32_t* winners, uint32_t num_frames, uint32_t k, uint32_t C,
+                  uint32_t* hist) {
+  for (uint32_t t = 0; t < num_frames; ++t) {
+    for (uint32_t j = 0; j < k; ++j) {
+      const int32_t c = winners[(size_t)t * k + j];
+      if (c < 0) continue; /* padding after the last winner */
+      if ((uint32_t)c >= C) return -1;
+      hist[c] += 1;
+    }
+  }
+  return 0;
+}

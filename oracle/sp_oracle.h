@@ -74,6 +74,14 @@ int spo_run(const spo_config* cfg, const uint32_t* idx, double* perm,
             const uint32_t* frames, uint32_t num_frames, int learn,
             int32_t* overlaps, int32_t* winners);
 
+/* Per-stream SDR histogram (Section 2: the pooler's output of every frame of
+ * a video is accumulated into a histogram that serves as the video's
+ * feature vector).  For every frame t < num_frames and every entry
+ * c = winners[t][j] >= 0, adds 1 to hist[c]; hist[C] is not cleared first.
+ * Returns 0, or -1 on an entry >= C. */
+int spo_histogram(const int32_t* winners, uint32_t num_frames, uint32_t k, uint32_t C,
+                  uint32_t* hist);
+
 #ifdef __cplusplus
 }
 #endif

@@ -26,7 +26,8 @@ from ._native import (SP_EBROKEN, SP_EDEVICE, SP_EINVAL, SP_ENOMEM, SP_INFER_GAT
 __all__ = [
     "SpError", "SpatialPooler", "synth", "sp_config_check", "sp_frame_words",
     "sp_workspace_bytes", "sp_check_state_host", "sp_create", "sp_check_state", "sp_step",
-    "sp_step_plain", "sp_infer", "sp_step_many", "sp_step_is_persistent", "sp_sync",
+    "sp_step_plain", "sp_infer", "sp_step_many", "sp_set_histogram", "sp_step_is_persistent",
+    "sp_sync",
     "sp_destroy",
     "sp_last_error", "SP_OK", "SP_EINVAL", "SP_ENOMEM", "SP_EDEVICE", "SP_EBROKEN",
     "SP_INFER_GATHER",
@@ -176,6 +177,15 @@ def sp_step_many(handles, cfgs, frames, learn: bool, overlaps, winners, stream=N
            "sp_step_many")
 
 
+def sp_set_histogram(h: int, hist=None) -> None:
+    """hist: uint32-sized int32 GPU tensor [C] that every later call of this
+    handle adds its winners to, or None to stop."""
+    if hist is not None:
+        assert hist.is_cuda and hist.is_contiguous() and hist.element_size() == 4
+    ptr = ctypes.c_void_p(hist.data_ptr()) if hist is not None else None
+    _check(lib().sp_set_histogram(ctypes.c_void_p(h), ptr), "sp_set_histogram")
+
+
 def sp_step_is_persistent(h: int) -> bool:
     return bool(_check(lib().sp_step_is_persistent(ctypes.c_void_p(h)), "sp_step_is_persistent"))
 
@@ -245,6 +255,12 @@ class SpatialPooler:
         win = torch.empty((F, self.cfg["winners"]), dtype=torch.int32, device=self.idx.device)
         sp_infer(self.handle, self.cfg, frames, mode, ov, win, stream)
         return ov, win
+
+    def set_histogram(self, hist=None) -> None:
+        """Accumulate every later call's winners into `hist` (GPU int32 [C],
+        kept alive here), or stop with None."""
+        sp_set_histogram(self.handle, hist)
+        self.hist = hist
 
     def sync(self, stream=None) -> None:
         sp_sync(self.handle, stream)

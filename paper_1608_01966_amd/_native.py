@@ -49,6 +49,7 @@ SIGNATURES = [
     ("sp_step_plain", ctypes.c_int, [P, P, U32, ctypes.c_int, P, P, P]),
     ("sp_infer", ctypes.c_int, [P, P, U32, ctypes.c_int, P, P, P]),
     ("sp_step_many", ctypes.c_int, [P, U32, P, P, ctypes.c_int, P, P, P]),
+    ("sp_set_histogram", ctypes.c_int, [P, P]),
     ("sp_step_is_persistent", ctypes.c_int, [P]),
     ("sp_sync", ctypes.c_int, [P, P]),
     ("sp_destroy", ctypes.c_int, [P]),

@@ -31,6 +31,7 @@ struct sp_handle {
   uint32_t* check;     // [4]
   int32_t* ov_scratch; // [C]
   uint32_t* many_ovx;  // [C] tagged overlaps of the many-instance step
+  uint32_t* hist;      // caller's [C] winner counts, or null
   uint64_t* many_dec;  // decision word of the many-instance step
   uint32_t many_steps; // steps this handle has taken through sp_step_many
   uint64_t xchg_frames;
@@ -164,6 +165,14 @@ int check_step_args(const sp_handle* h, const uint32_t* frames, uint32_t F, int3
   return SP_OK;
 }
 
+// The winners of a call added to the handle's histogram, if it has one.
+int add_histogram(const sp_handle* h, const int32_t* winners, uint32_t F, hipStream_t s) {
+  if (!h->hist || F == 0) return ok();
+  hipError_t e = htmsp::launch_hist_add(winners, (size_t)F * h->sh.k, h->sh.C, h->hist, s);
+  if (e != hipSuccess) return hip_fail(e, "histogram launch");
+  return ok();
+}
+
 // Spin polls one workgroup makes for one frame before it gives up (several
 // seconds; a correct launch needs a tiny fraction of it).
 constexpr uint32_t kSpinLimit = 1u << 21;
@@ -270,6 +279,79 @@ int many_slot(int device, size_t bytes, ManySlot** out) {
     sl.cap = cap;
   }
   *out = &sl;
+  return SP_OK;
+}
+
+// One cooperative launch over hs[0..n) (instances with frames; the caller
+// holds g_many_mu).  Tiles are dealt round-robin over the workgroups, top-k
+// tasks from the last workgroup backwards, so that in each workgroup tiles
+// come before top-k tasks and no workgroup holds more than kMaxTileSlots
+// tiles (tiles <= kMaxTileSlots * maxb).
+int many_launch(sp_handle* const* hs, uint32_t n, const uint32_t* const* frames_dev,
+                const uint32_t* num_frames, int learn, int32_t* const* overlaps_dev,
+                int32_t* const* winners_dev, hipStream_t s, int dev, int maxb, size_t ntiles,
+                uint32_t nact, uint32_t Fmax, uint32_t* err) {
+  const uint32_t ntasks = (uint32_t)(ntiles + nact);
+  const uint32_t grid = std::min<uint32_t>(ntasks, (uint32_t)maxb);
+  std::vector<std::vector<htmsp::ManyTask>> per(grid);
+  std::vector<htmsp::ManyInst> insts;
+  insts.reserve(nact);
+  uint32_t next_tile = 0, next_topk = 0;
+  for (uint32_t i = 0; i < n; ++i) {
+    sp_handle* h = hs[i];
+    if (num_frames[i] == 0) continue;
+    const uint32_t id = (uint32_t)insts.size();
+    htmsp::ManyInst in = {};
+    in.idx = h->idx;
+    in.perm = h->perm;
+    in.frames = frames_dev[i];
+    in.ov_out = overlaps_dev ? overlaps_dev[i] : nullptr;
+    in.win_out = winners_dev[i];
+    in.ovx = h->many_ovx;
+    in.dec = h->many_dec;
+    in.hist = h->hist;
+    in.sh = h->sh;
+    in.F = num_frames[i];
+    in.step_base = h->many_steps;
+    in.guess = 1 + h->sh.S / 16;
+    insts.push_back(in);
+    const uint32_t ct = htmsp::many_tile_columns(h->sh.S);
+    for (uint32_t c0 = 0; c0 < h->sh.C; c0 += ct)
+      per[next_tile++ % grid].push_back({id, 0u, c0, std::min(h->sh.C, c0 + ct)});
+  }
+  for (uint32_t id = 0; id < insts.size(); ++id)
+    per[grid - 1 - (next_topk++ % grid)].push_back({id, 1u, 0u, 0u});
+
+  const size_t b_insts = align_up(sizeof(htmsp::ManyInst) * insts.size(), 256);
+  const size_t b_tasks = align_up(sizeof(htmsp::ManyTask) * ntasks, 256);
+  const size_t b_off = sizeof(uint32_t) * (grid + 1);
+  ManySlot* sl = nullptr;
+  int rc = many_slot(dev, b_insts + b_tasks + b_off, &sl);
+  if (rc) return rc;
+  char* hb = static_cast<char*>(sl->host);
+  char* db = static_cast<char*>(sl->dev);
+  memcpy(hb, insts.data(), sizeof(htmsp::ManyInst) * insts.size());
+  htmsp::ManyTask* ht = reinterpret_cast<htmsp::ManyTask*>(hb + b_insts);
+  uint32_t* hoff = reinterpret_cast<uint32_t*>(hb + b_insts + b_tasks);
+  uint32_t k = 0;
+  for (uint32_t b = 0; b < grid; ++b) {
+    hoff[b] = k;
+    for (const auto& t : per[b]) ht[k++] = t;
+  }
+  hoff[grid] = k;
+  hipError_t e = hipMemcpyAsync(db, hb, b_insts + b_tasks + b_off, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "many-instance descriptors");
+  htmsp::ManyArgs a = {};
+  a.insts = reinterpret_cast<htmsp::ManyInst*>(db);
+  a.tasks = reinterpret_cast<const htmsp::ManyTask*>(db + b_insts);
+  a.task_off = reinterpret_cast<const uint32_t*>(db + b_insts + b_tasks);
+  a.err = err;
+  a.Fmax = Fmax;
+  a.learn = learn ? 1u : 0u;
+  a.spin_limit = kSpinLimit;
+  e = htmsp::launch_many(a, grid, s);
+  if (e == hipSuccess) e = hipEventRecord(sl->done, s);
+  if (e != hipSuccess) return hip_fail(e, "many-instance launch");
   return SP_OK;
 }
 
@@ -388,7 +470,7 @@ int sp_step_plain(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames,
     if (e == hipSuccess && learn) e = htmsp::launch_learn_plain(h->idx, h->perm, frame, win, sh, s);
     if (e != hipSuccess) return hip_fail(e, "plain step launch");
   }
-  return ok();
+  return add_histogram(h, winners_dev, num_frames, s);
 }
 
 int sp_step(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames, int learn,
@@ -420,7 +502,7 @@ int sp_step(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames, int l
   if (e != hipSuccess) return hip_fail(e, "persistent step launch");
   h->xchg_frames += (num_frames + 1) / 2;
   if (learn) ++h->state_version;
-  return ok();
+  return add_histogram(h, winners_dev, num_frames, static_cast<hipStream_t>(stream));
 }
 
 int sp_infer(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames, int mode,
@@ -484,7 +566,7 @@ int sp_infer(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames, int 
   else
     e = htmsp::launch_topk_plain(ov, winners_dev, sh, s, num_frames);
   if (e != hipSuccess) return hip_fail(e, "inference top-k launch");
-  return ok();
+  return add_histogram(h, winners_dev, num_frames, s);
 }
 
 int sp_step_many(sp_handle* const* hs, uint32_t n, const uint32_t* const* frames_dev,
@@ -494,8 +576,7 @@ int sp_step_many(sp_handle* const* hs, uint32_t n, const uint32_t* const* frames
   if (!hs || !frames_dev || !num_frames || !winners_dev)
     return fail(SP_EINVAL, "handles, frames, num_frames and winners arrays are required");
   int dev = -1;
-  uint32_t Fmax = 0;
-  size_t ntiles = 0, nact = 0;
+  size_t nact = 0;
   for (uint32_t i = 0; i < n; ++i) {
     const sp_handle* h = hs[i];
     int rc = check_step_args(h, frames_dev[i], num_frames[i],
@@ -509,9 +590,6 @@ int sp_step_many(sp_handle* const* hs, uint32_t n, const uint32_t* const* frames
     for (uint32_t j = 0; j < i; ++j)
       if (hs[j] == h) return fail(SP_EINVAL, "instance %u repeats instance %u", i, j);
     if (num_frames[i] == 0) continue;
-    Fmax = std::max(Fmax, num_frames[i]);
-    const uint32_t ct = htmsp::many_tile_columns(h->sh.S);
-    ntiles += (h->sh.C + ct - 1) / ct;
     ++nact;
   }
   if (nact == 0) return ok();
@@ -519,75 +597,52 @@ int sp_step_many(sp_handle* const* hs, uint32_t n, const uint32_t* const* frames
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int maxb = htmsp::many_max_blocks(dev);
   if (maxb <= 0) return fail(SP_EDEVICE, "cannot size the many-instance launch");
-  const uint32_t ntasks = (uint32_t)(ntiles + nact);
-  const uint32_t grid = std::min<uint32_t>(ntasks, (uint32_t)maxb);
-
-  // Tasks: tiles dealt round-robin over the blocks, top-k tasks from the
-  // last block backwards; in each block tiles come before top-k tasks.
-  std::vector<std::vector<htmsp::ManyTask>> per(grid);
-  std::vector<htmsp::ManyInst> insts;
-  insts.reserve(nact);
-  uint32_t next_tile = 0, next_topk = 0;
+  // Instances are independent, so they may be split over consecutive
+  // launches: each launch holds at most kMaxTileSlots tiles per workgroup.
+  const size_t cap = (size_t)htmsp::kMaxTileSlots * (size_t)maxb;
   for (uint32_t i = 0; i < n; ++i) {
-    sp_handle* h = hs[i];
-    if (num_frames[i] == 0) continue;
-    const uint32_t id = (uint32_t)insts.size();
-    htmsp::ManyInst in = {};
-    in.idx = h->idx;
-    in.perm = h->perm;
-    in.frames = frames_dev[i];
-    in.ov_out = overlaps_dev ? overlaps_dev[i] : nullptr;
-    in.win_out = winners_dev[i];
-    in.ovx = h->many_ovx;
-    in.dec = h->many_dec;
-    in.sh = h->sh;
-    in.F = num_frames[i];
-    in.step_base = h->many_steps;
-    in.guess = 1 + h->sh.S / 16;
-    insts.push_back(in);
-    const uint32_t ct = htmsp::many_tile_columns(h->sh.S);
-    for (uint32_t c0 = 0; c0 < h->sh.C; c0 += ct)
-      per[next_tile++ % grid].push_back({id, 0u, c0, std::min(h->sh.C, c0 + ct)});
+    const uint32_t ct = htmsp::many_tile_columns(hs[i]->sh.S);
+    const size_t nt = (hs[i]->sh.C + ct - 1) / ct;
+    if (num_frames[i] != 0 && nt > cap)
+      return fail(SP_EINVAL, "instance %u needs %zu tiles; one launch holds %zu on this device", i,
+                  nt, cap);
   }
-  for (uint32_t id = 0; id < insts.size(); ++id)
-    per[grid - 1 - (next_topk++ % grid)].push_back({id, 1u, 0u, 0u});
-
-  const size_t b_insts = align_up(sizeof(htmsp::ManyInst) * insts.size(), 256);
-  const size_t b_tasks = align_up(sizeof(htmsp::ManyTask) * ntasks, 256);
-  const size_t b_off = sizeof(uint32_t) * (grid + 1);
   std::lock_guard<std::mutex> lock(g_many_mu);
-  ManySlot* sl = nullptr;
-  int rc = many_slot(dev, b_insts + b_tasks + b_off, &sl);
-  if (rc) return rc;
-  char* hb = static_cast<char*>(sl->host);
-  char* db = static_cast<char*>(sl->dev);
-  memcpy(hb, insts.data(), sizeof(htmsp::ManyInst) * insts.size());
-  htmsp::ManyTask* ht = reinterpret_cast<htmsp::ManyTask*>(hb + b_insts);
-  uint32_t* hoff = reinterpret_cast<uint32_t*>(hb + b_insts + b_tasks);
-  uint32_t k = 0;
-  for (uint32_t b = 0; b < grid; ++b) {
-    hoff[b] = k;
-    for (const auto& t : per[b]) ht[k++] = t;
+  uint32_t i0 = 0;
+  while (i0 < n) {
+    uint32_t i1 = i0, nact_c = 0;
+    size_t tiles_c = 0;
+    uint32_t Fmax_c = 0;
+    for (; i1 < n; ++i1) {
+      if (num_frames[i1] == 0) continue;
+      const uint32_t ct = htmsp::many_tile_columns(hs[i1]->sh.S);
+      const size_t nt = (hs[i1]->sh.C + ct - 1) / ct;
+      if (nact_c > 0 && tiles_c + nt > cap) break;
+      tiles_c += nt;
+      ++nact_c;
+      Fmax_c = std::max(Fmax_c, num_frames[i1]);
+    }
+    if (nact_c > 0) {
+      int rc = many_launch(hs + i0, i1 - i0, frames_dev + i0, num_frames + i0, learn,
+                           overlaps_dev ? overlaps_dev + i0 : nullptr, winners_dev + i0, s, dev,
+                           maxb, tiles_c, nact_c, Fmax_c, hs[0]->err);
+      if (rc) return rc;
+    }
+    i0 = i1;
   }
-  hoff[grid] = k;
-  hipError_t e = hipMemcpyAsync(db, hb, b_insts + b_tasks + b_off, hipMemcpyHostToDevice, s);
-  if (e != hipSuccess) return hip_fail(e, "many-instance descriptors");
-  htmsp::ManyArgs a = {};
-  a.insts = reinterpret_cast<htmsp::ManyInst*>(db);
-  a.tasks = reinterpret_cast<const htmsp::ManyTask*>(db + b_insts);
-  a.task_off = reinterpret_cast<const uint32_t*>(db + b_insts + b_tasks);
-  a.err = hs[0]->err;
-  a.Fmax = Fmax;
-  a.learn = learn ? 1u : 0u;
-  a.spin_limit = kSpinLimit;
-  e = htmsp::launch_many(a, grid, s);
-  if (e == hipSuccess) e = hipEventRecord(sl->done, s);
-  if (e != hipSuccess) return hip_fail(e, "many-instance launch");
   for (uint32_t i = 0; i < n; ++i) {
     if (num_frames[i] == 0) continue;
     hs[i]->many_steps += num_frames[i];
     if (learn) ++hs[i]->state_version;
   }
+  return ok();
+}
+
+int sp_set_histogram(sp_handle* h, uint32_t* hist_dev) {
+  if (!h) return fail(SP_EINVAL, "handle is NULL");
+  if (hist_dev && ((uintptr_t)hist_dev & 3u))
+    return fail(SP_EINVAL, "histogram must be 4-byte aligned");
+  h->hist = hist_dev;
   return ok();
 }
 

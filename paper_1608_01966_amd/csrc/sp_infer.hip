@@ -10,6 +10,8 @@
 // workgroups that share a frame run on one XCD so its L2 serves them all.
 // A second kernel resolves the global top-k of every frame, one wave per
 // frame, on overlaps packed four per 64-bit word.
+#include <type_traits>
+
 #include "sp_device.h"
 #include "sp_internal.h"
 
@@ -26,6 +28,11 @@ constexpr uint32_t kInferThreads = 256;
 // reads only the low five bits of its offset) gives the bit.
 __device__ __forceinline__ uint32_t list_entry(uint32_t p) { return ((p >> 5) << 7) | (p & 31u); }
 __device__ __forceinline__ uint32_t entry_word(uint32_t e) { return e >> 7; }
+// The word of entry e in a frame staged at `fr`: bits 5 and 6 of an entry are
+// zero, so e >> 5 is already the word's byte offset (one shift, no mask).
+__device__ __forceinline__ uint32_t entry_load(const uint32_t* fr, uint32_t e) {
+  return *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(fr) + (e >> 5));
+}
 
 // Column c's connected inputs, slot-major: list[i * C + c] for i < cnt[c];
 // slots from cnt[c] to S - 1 hold `pad`, the entry of a word that is always
@@ -105,12 +112,98 @@ __global__ __launch_bounds__(kInferThreads) void k_infer_gather(
         for (int i = i0; i < i0 + 16; ++i) {
           const uint32_t e = lst[i];
           const uint32_t wi = entry_word(e);
-          const uint32_t word = LDS ? fr[wi] : (wi < sh.W ? frame[wi] : 0u);
+          const uint32_t word = LDS ? entry_load(fr, e) : (wi < sh.W ? frame[wi] : 0u);
           acc += __builtin_amdgcn_ubfe(word, e, 1);
         }
       }
     }
     if (col_ok) ov_out[(size_t)f * sh.C + c] = acc >= sh.m ? (int32_t)acc : 0;
+  }
+}
+
+// Gather overlaps with two frame buffers in LDS: while the workgroup counts
+// frame f from one buffer, frame f + 1 streams into the other with direct
+// global-to-LDS loads (no registers, no wait until the end of frame f).
+// One workgroup per CU (two 960x540 frames take 130 KB of LDS), THREADS
+// columns per workgroup; block ids map to (frame group, column block) as in
+// k_infer_gather.  The buffers sit at fixed LDS offsets so that the second
+// one is an immediate offset of the read.  `vec`: frames are 16-byte aligned
+// rows, so whole rows move in 16-byte pieces.
+constexpr uint32_t kDbBufWords = 16256;  // 65 024 B: the largest immediate-offset buffer
+
+template <int MAXN, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_infer_gather_db(
+    const uint32_t* __restrict__ frames, uint32_t F, const uint32_t* __restrict__ list,
+    const uint32_t* __restrict__ cnt, Shape sh, uint32_t frames_per_group, uint32_t col_blocks,
+    uint32_t groups, int32_t* __restrict__ ov_out, uint32_t vec) {
+  __shared__ uint32_t lds[2 * kDbBufWords];
+  const uint32_t per = 8 * col_blocks;
+  const uint32_t fg = (blockIdx.x / per) * 8 + blockIdx.x % 8;
+  const uint32_t cb = (blockIdx.x % per) / 8;
+  if (fg >= groups) return;  // whole workgroup
+  const uint32_t tid = threadIdx.x, lane = tid % kWave;
+  const uint32_t c = cb * THREADS + tid;
+  const bool col_ok = c < sh.C;
+  const uint32_t pad = sh.W << 7;
+
+  uint32_t lst[MAXN];
+#pragma unroll
+  for (int i = 0; i < MAXN; ++i)
+    lst[i] = (col_ok && (uint32_t)i < sh.S) ? list[(size_t)i * sh.C + c] : pad;
+  uint32_t n = col_ok ? cnt[c] : 0u;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) n = max(n, (uint32_t)__shfl_xor(n, off));
+
+  // Frame f into buffer b: the LDS address of a direct load is the wave's
+  // base plus the lane's offset, so the base passed is that of lane 0.
+  auto stage = [&](uint32_t f, uint32_t b) {
+    const uint32_t* fr = frames + (size_t)f * sh.W;
+    uint32_t* dst = lds + b * kDbBufWords;
+    if (vec) {
+      const uint32_t n4 = sh.W / 4;
+      for (uint32_t i = tid; i < n4; i += THREADS)
+        __builtin_amdgcn_global_load_lds(fr + 4 * i, dst + 4 * (i - lane), 16, 0, 0);
+    } else {
+      for (uint32_t i = tid; i < sh.W; i += THREADS)
+        __builtin_amdgcn_global_load_lds(fr + i, dst + (i - lane), 4, 0, 0);
+    }
+  };
+  // Counts frame f from buffer B, prefetching frame f + 1 into the other.
+  const uint32_t f0 = fg * frames_per_group;
+  const uint32_t f1 = min(F, f0 + frames_per_group);
+  auto frame = [&](uint32_t f, auto B) {
+    constexpr uint32_t b = decltype(B)::value;
+    if (f + 1 < f1) stage(f + 1, b ^ 1u);
+    const uint32_t* fr = lds + b * kDbBufWords;
+    // one register per list entry (see k_infer_gather)
+#pragma unroll
+    for (int i = 0; i < MAXN; ++i) asm volatile("" : "+v"(lst[i]));
+    uint32_t acc = 0;
+#pragma unroll
+    for (int i0 = 0; i0 < MAXN; i0 += 16) {
+      if ((uint32_t)i0 < n) {
+#pragma unroll
+        for (int i = i0; i < i0 + 16; ++i) {
+          const uint32_t e = lst[i];
+          acc += __builtin_amdgcn_ubfe(entry_load(fr, e), e, 1);
+        }
+      }
+    }
+    if (col_ok) ov_out[(size_t)f * sh.C + c] = acc >= sh.m ? (int32_t)acc : 0;
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+  };
+
+  if (tid == 0) {
+    lds[sh.W] = 0u;  // the padding entry's word, in both buffers
+    lds[kDbBufWords + sh.W] = 0u;
+  }
+  stage(f0, 0);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  for (uint32_t f = f0; f < f1; f += 2) {
+    frame(f, std::integral_constant<uint32_t, 0>());
+    if (f + 1 < f1) frame(f + 1, std::integral_constant<uint32_t, 1>());
   }
 }
 
@@ -192,6 +285,35 @@ hipError_t launch_gather_l(uint32_t maxn, const uint32_t* frames, uint32_t F,
   return launch_gather_t<256, LDS>(frames, F, list, cnt, sh, ov, cus, s);
 }
 
+template <int MAXN, int THREADS>
+hipError_t launch_gather_db_t(const uint32_t* frames, uint32_t F, const uint32_t* list,
+                              const uint32_t* cnt, const Shape& sh, int32_t* ov, uint32_t cus,
+                              hipStream_t s) {
+  const uint32_t col_blocks = (sh.C + THREADS - 1) / THREADS;
+  // one workgroup per CU, frame groups a multiple of 8
+  uint32_t groups = (cus + col_blocks - 1) / col_blocks;
+  groups = max(1u, min(groups, F));
+  const uint32_t fpg = (F + groups - 1) / groups;
+  groups = (F + fpg - 1) / fpg;
+  const uint32_t padded = (groups + 7) / 8 * 8;
+  const uint32_t vec = ((reinterpret_cast<uintptr_t>(frames) & 15u) == 0 && sh.W % 4 == 0);
+  hipLaunchKernelGGL((k_infer_gather_db<MAXN, THREADS>), dim3(padded * col_blocks),
+                     dim3(THREADS), 0, s, frames, F, list, cnt, sh, fpg, col_blocks, groups,
+                     ov, vec);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_db(uint32_t maxn, const uint32_t* frames, uint32_t F,
+                            const uint32_t* list, const uint32_t* cnt, const Shape& sh,
+                            int32_t* ov, uint32_t cus, hipStream_t s) {
+#define HTMSP_DB(M, T) \
+  if (maxn <= M) return launch_gather_db_t<M, T>(frames, F, list, cnt, sh, ov, cus, s);
+  HTMSP_DB(32, 512) HTMSP_DB(64, 512) HTMSP_DB(96, 512) HTMSP_DB(128, 512)
+  HTMSP_DB(160, 512) HTMSP_DB(192, 512) HTMSP_DB(224, 256)
+#undef HTMSP_DB
+  return launch_gather_db_t<256, 256>(frames, F, list, cnt, sh, ov, cus, s);
+}
+
 }  // namespace
 
 uint32_t infer_max_list() { return 256; }
@@ -210,6 +332,14 @@ hipError_t launch_infer_prep(const uint32_t* idx, const float* perm, const Shape
 hipError_t launch_infer_gather(uint32_t maxn, const uint32_t* frames, uint32_t F,
                                const uint32_t* list, const uint32_t* cnt, const Shape& sh,
                                int32_t* ov, uint32_t cus, hipStream_t s) {
+  int dev = 0, lds_max = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess)
+    e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  if (e != hipSuccess) return e;
+  // two buffers, each the frame plus the zero word
+  if (sh.W + 1 <= kDbBufWords && sizeof(uint32_t) * 2 * kDbBufWords <= (size_t)lds_max)
+    return launch_gather_db(maxn, frames, F, list, cnt, sh, ov, cus, s);
   const bool lds = sizeof(uint32_t) * ((size_t)sh.W + 1) <= infer_lds_limit();
   return lds ? launch_gather_l<true>(maxn, frames, F, list, cnt, sh, ov, cus, s)
              : launch_gather_l<false>(maxn, frames, F, list, cnt, sh, ov, cus, s);

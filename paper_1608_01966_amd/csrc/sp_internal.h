@@ -78,11 +78,16 @@ hipError_t launch_infer_gather(uint32_t maxn, const uint32_t* frames, uint32_t F
 hipError_t launch_topk_batch(const int32_t* ov, uint32_t F, const Shape& sh, int32_t* winners,
                              hipStream_t s);
 
+// Adds 1 to hist[c] for every entry c >= 0 of winners[n] (sp_hist.hip).
+hipError_t launch_hist_add(const int32_t* winners, size_t n, uint32_t C, uint32_t* hist,
+                           hipStream_t s);
+
 // Many instances in one persistent launch (sp_many.hip).
 constexpr uint32_t kManyNV = 16;          // top-k words per lane: C <= 4096
 constexpr uint32_t kTileSynapses = 8192;  // synapses per tile task (at most)
 constexpr uint32_t kTileColumns = 1024;   // columns per tile task (at most)
 constexpr uint32_t kManyThreads = 256;
+constexpr uint32_t kMaxTileSlots = 16;    // tile tasks per workgroup (at most)
 
 struct ManyInst {
   const uint32_t* idx;
@@ -92,6 +97,7 @@ struct ManyInst {
   int32_t* win_out;        // [F][k]
   uint32_t* ovx;           // [C] tagged overlaps
   uint64_t* dec;           // decision word
+  uint32_t* hist;          // [C] winner counts to add to, or null
   Shape sh;
   uint32_t F, step_base, guess, pad;
 };

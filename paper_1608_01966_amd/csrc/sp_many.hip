@@ -11,10 +11,13 @@
 //     the whole workgroup: for step t it applies learning of frame t-1 to its
 //     winning columns, then computes the overlaps of frame t and publishes
 //     them.  Each thread owns up to 32 synapses of the tile's flat
-//     [column][synapse] range and issues all their loads, then all their
-//     input gathers, at once; per-column counts are summed in LDS.
+//     [column][synapse] range and issues all their state loads before the
+//     wait for the previous decision, then both input gathers at once;
+//     per-column counts are summed in LDS, and each tile keeps its last
+//     published overlaps in LDS to decide its winners.
 //   top-k task (instance), wave 0: for step t it collects the instance's
-//     overlaps, resolves the global top-k, writes the frame's outputs and
+//     overlaps, resolves the global top-k, writes the frame's outputs (and
+//     adds the winners to the instance's histogram, if it has one) and
 //     publishes a decision word from which every tile derives which of its
 //     columns won.
 // Synapse state is read from and written to device memory every step (the
@@ -70,14 +73,15 @@ __device__ __forceinline__ uint32_t div_s(uint32_t p, uint32_t S, float invS) {
 }
 
 struct TileLds {
-  uint32_t cnt[kTileColumns];  // raw overlap counts of the step
-  uint8_t won[kTileColumns];   // column won the previous frame
-  uint32_t bc[3];              // ok, T, last tied winner + 1
+  uint32_t cnt[kTileColumns];                 // raw overlap counts of the step
+  uint16_t prev[kMaxTileSlots][kTileColumns];  // each tile's published overlaps of the last step
+  uint32_t bc[3];                             // ok, T, last tied winner + 1
 };
 
-// Tile task, whole workgroup.  Returns false (uniformly) on abort.
+// Tile task `slot` of this workgroup, whole workgroup.  Returns false
+// (uniformly) on abort.
 __device__ bool tile_step(const ManyArgs& a, const ManyInst& in, uint32_t c0, uint32_t c1,
-                          uint32_t t, TileLds& L) {
+                          uint32_t t, uint32_t slot, TileLds& L) {
   const Shape& sh = in.sh;
   const uint32_t tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
   const uint32_t tag_prev = (in.step_base + t) & 0xFFFFu;  // tag of step t - 1
@@ -86,6 +90,20 @@ __device__ bool tile_step(const ManyArgs& a, const ManyInst& in, uint32_t c0, ui
   const bool learn_now = a.learn && t > 0;
   const bool overlap_now = t < in.F;
 
+  // The state does not depend on the decision: its loads are in flight
+  // while thread 0 waits.
+  const size_t p0 = (size_t)c0 * sh.S;
+  const uint32_t* gidx = in.idx + p0;
+  float* gperm = in.perm + p0;
+  const float invS = 1.0f / (float)sh.S;
+  uint32_t ix[kPerThread], q[kPerThread];
+#pragma unroll
+  for (uint32_t j = 0; j < kPerThread; ++j) {
+    const uint32_t p = tid + kManyThreads * j;
+    const bool v = p < nsyn;
+    ix[j] = v ? min(gidx[p], sh.N - 1) : 0u;
+    q[j] = v ? perm_to_q(gperm[p]) : 0u;
+  }
   if (tid == 0) {
     uint64_t d = 0;
     const bool ok = t == 0 || wait_decision(in, tag_prev, a, &d);
@@ -95,60 +113,44 @@ __device__ bool tile_step(const ManyArgs& a, const ManyInst& in, uint32_t c0, ui
   }
   __syncthreads();
   if (!L.bc[0]) return false;
-  if (learn_now) {
-    const uint32_t T = L.bc[1], clast1 = L.bc[2];
-    // the column's own overlap of frame t - 1 is still in its exchange entry
-    for (uint32_t cl = tid; cl < ncol; cl += kManyThreads) {
-      const uint32_t c = c0 + cl;
-      const uint32_t prev = load_tagged(in.ovx + c) & 0xFFFFu;
-      L.won[cl] = prev > T || (T != 0 && prev == T && c + 1 <= clast1);
-    }
-  }
-  __syncthreads();
+  const uint32_t T = L.bc[1], clast1 = L.bc[2];
 
-  const size_t p0 = (size_t)c0 * sh.S;
-  const uint32_t* gidx = in.idx + p0;
-  float* gperm = in.perm + p0;
-  const float invS = 1.0f / (float)sh.S;
-  uint32_t ix[kPerThread], q[kPerThread], w[kPerThread];
+  // Which synapses belong to a column that won frame t - 1 (its overlap of
+  // that frame is the one this tile published last step), then both input
+  // gathers in one round: frame t - 1 for learning, frame t for every
+  // synapse that can be connected after learning.
+  const uint32_t* fprev = in.frames + (size_t)(learn_now ? t - 1 : 0) * sh.W;
+  const uint32_t* fcur = in.frames + (size_t)(overlap_now ? t : 0) * sh.W;
+  uint32_t won = 0;  // bit j: synapse j belongs to a winner
+  uint32_t wp[kPerThread], wc[kPerThread];
 #pragma unroll
   for (uint32_t j = 0; j < kPerThread; ++j) {
     const uint32_t p = tid + kManyThreads * j;
-    const bool v = p < nsyn;
-    ix[j] = v ? min(gidx[p], sh.N - 1) : 0u;
-    q[j] = v ? perm_to_q(gperm[p]) : 0u;
+    bool wj = false;
+    if (learn_now && p < nsyn) {
+      const uint32_t cl = div_s(p, sh.S, invS);
+      const uint32_t prev = L.prev[slot][cl];
+      wj = prev > T || (T != 0 && prev == T && c0 + cl + 1 <= clast1);
+    }
+    won |= (uint32_t)wj << j;
+    wp[j] = wj ? fprev[ix[j] >> 5] : 0u;
+    const bool maybe = overlap_now && p < nsyn && (wj ? q[j] + sh.inc : q[j]) >= sh.theta;
+    wc[j] = maybe ? fcur[ix[j] >> 5] : 0u;
   }
-  if (learn_now) {
-    const uint32_t* fprev = in.frames + (size_t)(t - 1) * sh.W;
-    uint32_t won = 0;  // bit j: synapse j belongs to a winner
+  if (won) {
 #pragma unroll
     for (uint32_t j = 0; j < kPerThread; ++j) {
-      const uint32_t p = tid + kManyThreads * j;
-      const bool wj = p < nsyn && L.won[div_s(p, sh.S, invS)];
-      won |= (uint32_t)wj << j;
-      w[j] = wj ? fprev[ix[j] >> 5] : 0u;
-    }
-    if (won) {
-#pragma unroll
-      for (uint32_t j = 0; j < kPerThread; ++j) {
-        if (won & (1u << j)) {
-          q[j] = learn_q(q[j], input_bit(w[j], ix[j]), sh);
-          gperm[tid + kManyThreads * j] = q_to_perm(q[j]);
-        }
+      if (won & (1u << j)) {
+        q[j] = learn_q(q[j], input_bit(wp[j], ix[j]), sh);
+        gperm[tid + kManyThreads * j] = q_to_perm(q[j]);
       }
     }
   }
   if (overlap_now) {
-    const uint32_t* fcur = in.frames + (size_t)t * sh.W;
-#pragma unroll
-    for (uint32_t j = 0; j < kPerThread; ++j) {
-      const uint32_t p = tid + kManyThreads * j;
-      w[j] = (p < nsyn && q[j] >= sh.theta) ? fcur[ix[j] >> 5] : 0u;
-    }
 #pragma unroll
     for (uint32_t j = 0; j < kPerThread; ++j) {
       const uint32_t pb = kManyThreads * j + kWave * wave;  // first flat position of the chunk
-      const bool hit = (pb + lane < nsyn) && q[j] >= sh.theta && input_bit(w[j], ix[j]);
+      const bool hit = (pb + lane < nsyn) && q[j] >= sh.theta && input_bit(wc[j], ix[j]);
       const uint64_t mask = __ballot(hit);
       if (pb < nsyn && mask) {
         // columns that meet the chunk [pb, pb + 64): lane l counts column clA + l
@@ -171,6 +173,7 @@ __device__ bool tile_step(const ManyArgs& a, const ManyInst& in, uint32_t c0, ui
       const uint32_t raw = L.cnt[cl];
       L.cnt[cl] = 0;
       const uint32_t ov = raw >= sh.m ? raw : 0u;
+      L.prev[slot][cl] = (uint16_t)ov;
       store_tagged(in.ovx + c0 + cl, (tag << 16) | ov);
     }
   }
@@ -260,6 +263,8 @@ __device__ bool topk_step(const ManyArgs& a, ManyInst& in, uint32_t t, uint32_t 
         if (sel & (0x8000ull << (16 * q))) {
           wrow[pos] = (int32_t)c;
           ++pos;
+          // this wave is the instance's only histogram writer in the launch
+          if (in.hist) in.hist[c] += 1u;
         }
         if (eq & (0x8000ull << (16 * q))) clast1 = max(clast1, c + 1);
         if (in.ov_out && c < sh.C)
@@ -295,7 +300,8 @@ __global__ __launch_bounds__(kManyThreads, 2) void k_sp_many(ManyArgs a) {
       ManyInst& in = a.insts[task.inst];
       if (t > in.F) continue;
       if (task.kind == 0) {
-        ok = tile_step(a, in, task.c0, task.c1, t, L);
+        // the host deals at most kMaxTileSlots tiles, first, to a workgroup
+        ok = j - t0 < kMaxTileSlots && tile_step(a, in, task.c0, task.c1, t, j - t0, L);
       } else if (t < in.F && wave == 0) {
         ok = topk_step(a, in, t, lane);
       }

@@ -199,14 +199,18 @@ class GpuBackend:
 
     def stream_bytes(self, spec: StreamSpec) -> int:
         C, S = spec.cfg["num_columns"], spec.cfg["synapses_per_column"]
-        return 8 * C * S + int(self._ws_bytes(spec.cfg))
+        return 8 * C * S + 4 * C + int(self._ws_bytes(spec.cfg))
 
     def open(self, spec: StreamSpec):
         from . import SpatialPooler
         pool = SpatialPooler(spec.cfg, spec.idx, spec.perm, stream=self.stream)
         win = (self.torch.empty((len(spec.arrivals), spec.cfg["winners"]),
                                 dtype=self.torch.int32, device="cuda") if self.keep else None)
-        return {"pool": pool, "win": win}
+        # the stream's SDR histogram (Section 2's per-video feature vector)
+        hist = self.torch.zeros(spec.cfg["num_columns"], dtype=self.torch.int32, device="cuda")
+        self.torch.cuda.current_stream().synchronize()
+        pool.set_histogram(hist)
+        return {"pool": pool, "win": win, "hist": hist}
 
     def close(self, h):
         h["pool"].close()

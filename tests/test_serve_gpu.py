@@ -33,16 +33,19 @@ def test_streams_equal_alone_in_the_mix():
 
     def close_(h):
         h["pool"].sync(be.stream)
-        finals[id(h)] = (h["win"].cpu().numpy(), h["pool"].perm.cpu().numpy())
+        finals[id(h)] = (h["win"].cpu().numpy(), h["pool"].perm.cpu().numpy(),
+                         h["hist"].cpu().numpy())
         orig_close(h)
     be.close = close_
     srv.run()
     assert max(srv.batch_sizes) > 1
     assert srv.peak_used <= srv.budget
     for spec in specs:
-        win, perm = finals[id(handles[spec.sid])]
+        win, perm, hist = finals[id(handles[spec.sid])]
         e_ov, e_win, e_perm = oracle.run(spec.cfg, spec.idx, spec.perm, frames[spec.frame_ids])
         assert np.array_equal(win, e_win), f"stream {spec.sid}"
         assert np.array_equal(perm.astype(np.float64), e_perm), f"stream {spec.sid}"
+        assert np.array_equal(hist.astype(np.uint32),
+                              oracle.histogram(e_win, spec.cfg["num_columns"])), f"stream {spec.sid}"
     lat = srv.latencies()
     assert lat.size == sum(len(s.arrivals) for s in specs) and np.all(lat > 0)

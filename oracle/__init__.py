@@ -28,7 +28,7 @@ def build() -> str:
     tmp = _LIB_PATH + ".tmp"
     subprocess.check_call([
         "gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-Werror", "-fPIC", "-shared",
-        os.path.join(_HERE, "sp_oracle.c"), "-o", tmp,
+        os.path.join(_HERE, "sp_oracle.c"), os.path.join(_HERE, "enc_oracle.c"), "-o", tmp,
     ])
     os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -44,6 +44,16 @@ class _Cfg(ctypes.Structure):
         ("connected_perm", ctypes.c_double),
         ("perm_inc", ctypes.c_double),
         ("perm_dec", ctypes.c_double),
+    ]
+
+
+class _EncCfg(ctypes.Structure):
+    _fields_ = [
+        ("width", ctypes.c_uint32),
+        ("height", ctypes.c_uint32),
+        ("factor", ctypes.c_uint32),
+        ("block", ctypes.c_uint32),
+        ("offset", ctypes.c_int32),
     ]
 
 
@@ -67,6 +77,17 @@ def _load():
         lib.spo_run.restype = ctypes.c_int
         lib.spo_histogram.argtypes = [P, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, P]
         lib.spo_histogram.restype = ctypes.c_int
+        lib.enc_reduce.argtypes = [P, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, P]
+        lib.enc_reduce.restype = None
+        lib.enc_gray.argtypes = [P, ctypes.c_uint32, P]
+        lib.enc_gray.restype = None
+        lib.enc_threshold.argtypes = [P, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                      ctypes.c_int32, P]
+        lib.enc_threshold.restype = None
+        lib.enc_pack.argtypes = [P, ctypes.c_uint32, P]
+        lib.enc_pack.restype = None
+        lib.enc_frames.argtypes = [ctypes.POINTER(_EncCfg), P, ctypes.c_uint32, P]
+        lib.enc_frames.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -155,3 +176,50 @@ def histogram(winners: np.ndarray, num_columns: int, hist: np.ndarray | None = N
     if _load().spo_histogram(_ptr(w), F, k, int(num_columns), _ptr(h)) != 0:
         raise ValueError("winner index out of range")
     return h
+
+
+# ---- adaptive video encoder (Section 3.1.2), readings E1-E6 in enc_oracle.h
+
+def enc_reduce(rgb: np.ndarray, factor: int) -> np.ndarray:
+    """uint8 [H][W][3] -> uint8 [H/f][W/f][3], block means rounded half up."""
+    rgb = np.ascontiguousarray(rgb, dtype=np.uint8)
+    H, W = rgb.shape[:2]
+    out = np.zeros((H // factor, W // factor, 3), dtype=np.uint8)
+    _load().enc_reduce(_ptr(rgb), W, H, int(factor), _ptr(out))
+    return out
+
+
+def enc_gray(rgb: np.ndarray) -> np.ndarray:
+    """uint8 [..., 3] -> uint8 [...] BT.601 luma in 14-bit fixed point."""
+    rgb = np.ascontiguousarray(rgb, dtype=np.uint8)
+    out = np.zeros(rgb.shape[:-1], dtype=np.uint8)
+    _load().enc_gray(_ptr(rgb), int(out.size), _ptr(out))
+    return out
+
+
+def enc_threshold(gray: np.ndarray, block: int, offset: int) -> np.ndarray:
+    """uint8 [h][w] -> uint8 0/1 [h][w]: Y > binomial-window mean - offset."""
+    gray = np.ascontiguousarray(gray, dtype=np.uint8)
+    h, w = gray.shape
+    on = np.zeros((h, w), dtype=np.uint8)
+    _load().enc_threshold(_ptr(gray), w, h, int(block), int(offset), _ptr(on))
+    return on
+
+
+def enc_pack(on: np.ndarray) -> np.ndarray:
+    on = np.ascontiguousarray(on, dtype=np.uint8).reshape(-1)
+    words = np.zeros((on.size + 31) // 32, dtype=np.uint32)
+    _load().enc_pack(_ptr(on), int(on.size), _ptr(words))
+    return words
+
+
+def enc_frames(rgb: np.ndarray, factor: int = 1, block: int = 11, offset: int = 2) -> np.ndarray:
+    """uint8 [F][H][W][3] -> uint32 [F][ceil(w h / 32)] packed binary frames."""
+    rgb = np.ascontiguousarray(rgb, dtype=np.uint8)
+    F, H, W = rgb.shape[:3]
+    n = (W // factor) * (H // factor)
+    words = np.zeros((F, (n + 31) // 32), dtype=np.uint32)
+    c = _EncCfg(W, H, int(factor), int(block), int(offset))
+    if _load().enc_frames(ctypes.byref(c), _ptr(rgb), F, _ptr(words)) != 0:
+        raise ValueError("encoder oracle rejected its configuration")
+    return words

@@ -77,6 +77,12 @@ def _load():
         lib.spo_run.restype = ctypes.c_int
         lib.spo_histogram.argtypes = [P, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, P]
         lib.spo_histogram.restype = ctypes.c_int
+        lib.spo_inhibit_local.argtypes = [P, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                          ctypes.c_uint32, P]
+        lib.spo_inhibit_local.restype = ctypes.c_int
+        lib.spo_run_local.argtypes = [ctypes.POINTER(_Cfg), P, P, P, ctypes.c_uint32, ctypes.c_int,
+                                      ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, P, P]
+        lib.spo_run_local.restype = ctypes.c_int
         lib.enc_reduce.argtypes = [P, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, P]
         lib.enc_reduce.restype = None
         lib.enc_gray.argtypes = [P, ctypes.c_uint32, P]
@@ -176,6 +182,37 @@ def histogram(winners: np.ndarray, num_columns: int, hist: np.ndarray | None = N
     if _load().spo_histogram(_ptr(w), F, k, int(num_columns), _ptr(h)) != 0:
         raise ValueError("winner index out of range")
     return h
+
+
+def inhibit_local(overlap: np.ndarray, grid_w: int, radius: int, n: int) -> np.ndarray:
+    """Algorithm 2 with a neighbourhood (readings L1-L4): uint8 [C] active."""
+    ov = np.ascontiguousarray(overlap, dtype=np.int32).reshape(-1)
+    act = np.zeros(ov.size, dtype=np.uint8)
+    if _load().spo_inhibit_local(_ptr(ov), ov.size, int(grid_w), int(radius), int(n),
+                                 _ptr(act)) < 0:
+        raise ValueError("bad local inhibition arguments")
+    return act
+
+
+def run_local(cfg: dict, idx: np.ndarray, perm: np.ndarray, frames: np.ndarray, grid_w: int,
+              radius: int, n: int, learn: bool = True, want_overlaps: bool = True):
+    """F frames with local inhibition.  Returns (overlaps int32 [F][C] or
+    None, active uint8 [F][C], perm float64 [C][S])."""
+    idx = np.ascontiguousarray(idx, dtype=np.uint32)
+    perm = np.array(perm, dtype=np.float64, order="C", copy=True)
+    frames = np.ascontiguousarray(frames, dtype=np.uint32)
+    F = frames.shape[0] if frames.ndim == 2 else (0 if frames.size == 0 else 1)
+    frames = frames.reshape(F, _words(cfg))
+    C = int(cfg["num_columns"])
+    ov = np.zeros((F, C), dtype=np.int32) if want_overlaps else None
+    act = np.zeros((F, C), dtype=np.uint8)
+    c = _cfg(cfg)
+    rc = _load().spo_run_local(ctypes.byref(c), _ptr(idx), _ptr(perm), _ptr(frames), F,
+                               int(bool(learn)), int(grid_w), int(radius), int(n),
+                               _ptr(ov) if ov is not None else None, _ptr(act))
+    if rc != 0:
+        raise ValueError("oracle rejected its arguments")
+    return ov, act, perm
 
 
 # ---- adaptive video encoder (Section 3.1.2), readings E1-E6 in enc_oracle.h

@@ -134,3 +134,59 @@ int spo_histogram(const int32_t* winners, uint32_t num_frames, uint32_t k, uint3
   }
   return 0;
 }
+
+static int cmp_desc(const void* a, const void* b) {
+  const int32_t x = *(const int32_t*)a, y = *(const int32_t*)b;
+  return (x < y) - (x > y);
+}
+
+int spo_inhibit_local(const int32_t* overlap, uint32_t C, uint32_t grid_w, uint32_t radius,
+                      uint32_t n, uint8_t* active) {
+  if (C == 0 || grid_w == 0 || n == 0) return -1;
+  int32_t* nb = (int32_t*)malloc(sizeof(int32_t) * C);
+  if (!nb) return -1;
+  int count = 0;
+  for (uint32_t c = 0; c < C; ++c) {
+    const int64_t cx = c % grid_w, cy = c / grid_w;
+    uint32_t m = 0;
+    for (uint32_t d = 0; d < C; ++d) {
+      if (d == c) continue;
+      const int64_t dx = (int64_t)(d % grid_w) - cx, dy = (int64_t)(d / grid_w) - cy;
+      if (dx <= (int64_t)radius && -dx <= (int64_t)radius && dy <= (int64_t)radius &&
+          -dy <= (int64_t)radius)
+        nb[m++] = overlap[d];
+    }
+    /* n_max_overlap: the n-th largest neighbour overlap */
+    qsort(nb, m, sizeof(int32_t), cmp_desc);
+    const int32_t nth = m >= n ? nb[n - 1] : 0;
+    const int32_t max_column = nth > 1 ? nth : 1;
+    active[c] = overlap[c] > max_column ? 1 : 0;
+    count += active[c];
+  }
+  free(nb);
+  return count;
+}
+
+int spo_run_local(const spo_config* cfg, const uint32_t* idx, double* perm,
+                  const uint32_t* frames, uint32_t num_frames, int learn, uint32_t grid_w,
+                  uint32_t radius, uint32_t n, int32_t* overlaps, uint8_t* active) {
+  if (!cfg || !idx || !perm || (!frames && num_frames) || (!active && num_frames)) return -1;
+  const uint32_t C = cfg->num_columns;
+  if (C == 0 || cfg->synapses_per_column == 0 || cfg->input_bits == 0 || grid_w == 0 || n == 0)
+    return -1;
+  const size_t W = ((size_t)cfg->input_bits + 31) / 32;
+  for (size_t i = 0; i < (size_t)C * cfg->synapses_per_column; ++i)
+    if (idx[i] >= cfg->input_bits) return -1;
+  int32_t* ov = (int32_t*)malloc(sizeof(int32_t) * C);
+  if (!ov) return -1;
+  for (uint32_t t = 0; t < num_frames; ++t) {
+    const uint32_t* frame = frames + (size_t)t * W;
+    uint8_t* act = active + (size_t)t * C;
+    spo_overlap(cfg, idx, perm, frame, ov);
+    spo_inhibit_local(ov, C, grid_w, radius, n, act);
+    if (learn) spo_learn(cfg, idx, perm, frame, act);
+    if (overlaps) memcpy(overlaps + (size_t)t * C, ov, sizeof(int32_t) * C);
+  }
+  free(ov);
+  return 0;
+}

@@ -74,6 +74,27 @@ int spo_run(const spo_config* cfg, const uint32_t* idx, double* perm,
             const uint32_t* frames, uint32_t num_frames, int learn,
             int32_t* overlaps, int32_t* winners);
 
+/* Local inhibition, Algorithm 2 as printed (the radius form Section 3.2.2
+ * describes), on one frame's gated overlaps.  Columns sit on a grid of
+ * grid_w columns per row (row-major; C need not fill the last row).  The
+ * neighbourhood of c is every other column d whose row and column
+ * coordinates differ from c's by at most `radius` (no wrap-around); the
+ * n-th largest overlap among the neighbours (0 when there are fewer than n)
+ * gives max_column = max(that, 1), and c is active iff its overlap >
+ * max_column.  Readings L1-L4 (grid, neighbourhood without c, strict
+ * comparison, the 1 floor) are listed in the design notes.  Writes
+ * active[C]; returns the number of active columns, -1 on a bad argument. */
+int spo_inhibit_local(const int32_t* overlap, uint32_t C, uint32_t grid_w, uint32_t radius,
+                      uint32_t n, uint8_t* active);
+
+/* F frames in order with local inhibition: overlap (Algorithm 1), local
+ * inhibition, and, when learn != 0, learning (R5) on the active columns.
+ * overlaps [F][C] may be NULL; active is [F][C].  Returns 0, -1 on a bad
+ * argument. */
+int spo_run_local(const spo_config* cfg, const uint32_t* idx, double* perm,
+                  const uint32_t* frames, uint32_t num_frames, int learn, uint32_t grid_w,
+                  uint32_t radius, uint32_t n, int32_t* overlaps, uint8_t* active);
+
 /* Per-stream SDR histogram (Section 2: the pooler's output of every frame of
  * a video is accumulated into a histogram that serves as the video's
  * feature vector).  For every frame t < num_frames and every entry

@@ -47,6 +47,15 @@ class _Cfg(ctypes.Structure):
     ]
 
 
+class _Boost(ctypes.Structure):
+    _fields_ = [
+        ("period_log2", ctypes.c_uint32),
+        ("min_pct_q16", ctypes.c_uint32),
+        ("max_boost_q8", ctypes.c_uint32),
+        ("bump_q8", ctypes.c_uint32),
+    ]
+
+
 class _EncCfg(ctypes.Structure):
     _fields_ = [
         ("width", ctypes.c_uint32),
@@ -77,6 +86,9 @@ def _load():
         lib.spo_run.restype = ctypes.c_int
         lib.spo_histogram.argtypes = [P, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, P]
         lib.spo_histogram.restype = ctypes.c_int
+        lib.spo_run_boost.argtypes = [ctypes.POINTER(_Cfg), ctypes.POINTER(_Boost), P, P, P,
+                                      ctypes.c_uint32, ctypes.c_int, P, P, P, P, P]
+        lib.spo_run_boost.restype = ctypes.c_int
         lib.spo_inhibit_local.argtypes = [P, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
                                           ctypes.c_uint32, P]
         lib.spo_inhibit_local.restype = ctypes.c_int
@@ -182,6 +194,40 @@ def histogram(winners: np.ndarray, num_columns: int, hist: np.ndarray | None = N
     if _load().spo_histogram(_ptr(w), F, k, int(num_columns), _ptr(h)) != 0:
         raise ValueError("winner index out of range")
     return h
+
+
+def boost_state(num_columns: int):
+    """Initial boosting state: duty cycles 0, boosts 1 (256 in 1/256)."""
+    C = int(num_columns)
+    return (np.zeros(C, dtype=np.uint32), np.zeros(C, dtype=np.uint32),
+            np.full(C, 256, dtype=np.uint32))
+
+
+def run_boost(cfg: dict, bcfg: dict, idx: np.ndarray, perm: np.ndarray, frames: np.ndarray,
+              learn: bool = True, state=None, want_overlaps: bool = True):
+    """F frames with boosting (readings B1-B7).  bcfg: period_log2,
+    min_pct_q16, max_boost_q8, bump_q8.  state: (adc, odc, boost) uint32 [C]
+    or None for the initial state.  Returns (boosted overlaps int32 [F][C] or
+    None, winners int32 [F][k], perm float64, (adc, odc, boost))."""
+    idx = np.ascontiguousarray(idx, dtype=np.uint32)
+    perm = np.array(perm, dtype=np.float64, order="C", copy=True)
+    frames = np.ascontiguousarray(frames, dtype=np.uint32)
+    F = frames.shape[0] if frames.ndim == 2 else (0 if frames.size == 0 else 1)
+    frames = frames.reshape(F, _words(cfg))
+    C, k = int(cfg["num_columns"]), int(cfg["winners"])
+    adc, odc, boost = (boost_state(C) if state is None
+                       else tuple(np.array(a, dtype=np.uint32, copy=True) for a in state))
+    ov = np.zeros((F, C), dtype=np.int32) if want_overlaps else None
+    win = np.zeros((F, k), dtype=np.int32)
+    b = _Boost(int(bcfg["period_log2"]), int(bcfg["min_pct_q16"]), int(bcfg["max_boost_q8"]),
+               int(bcfg["bump_q8"]))
+    c = _cfg(cfg)
+    rc = _load().spo_run_boost(ctypes.byref(c), ctypes.byref(b), _ptr(idx), _ptr(perm),
+                               _ptr(frames), F, int(bool(learn)), _ptr(adc), _ptr(odc),
+                               _ptr(boost), _ptr(ov) if ov is not None else None, _ptr(win))
+    if rc != 0:
+        raise ValueError("oracle rejected its arguments")
+    return ov, win, perm, (adc, odc, boost)
 
 
 def inhibit_local(overlap: np.ndarray, grid_w: int, radius: int, n: int) -> np.ndarray:

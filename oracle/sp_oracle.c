@@ -190,3 +190,66 @@ int spo_run_local(const spo_config* cfg, const uint32_t* idx, double* perm,
   free(ov);
   return 0;
 }
+
+int spo_run_boost(const spo_config* cfg, const spo_boost* bc, const uint32_t* idx, double* perm,
+                  const uint32_t* frames, uint32_t num_frames, int learn, uint32_t* adc,
+                  uint32_t* odc, uint32_t* boost, int32_t* overlaps, int32_t* winners) {
+  if (!cfg || !bc || !idx || !perm || !adc || !odc || !boost) return -1;
+  if ((!frames || !winners) && num_frames) return -1;
+  const uint32_t C = cfg->num_columns, S = cfg->synapses_per_column, k = cfg->winners;
+  if (C == 0 || S == 0 || k == 0 || k > C || cfg->input_bits == 0) return -1;
+  if (bc->period_log2 > 16 || bc->max_boost_q8 < 256 || bc->max_boost_q8 > 4096 ||
+      bc->min_pct_q16 > 65536 || bc->bump_q8 > 256)
+    return -1;
+  const size_t W = ((size_t)cfg->input_bits + 31) / 32;
+  for (size_t i = 0; i < (size_t)C * S; ++i)
+    if (idx[i] >= cfg->input_bits) return -1;
+  const uint64_t P = 1ull << bc->period_log2;
+  int32_t* ov = (int32_t*)malloc(sizeof(int32_t) * C);
+  int32_t* bov = (int32_t*)malloc(sizeof(int32_t) * C);
+  uint8_t* active = (uint8_t*)malloc(C);
+  if (!ov || !bov || !active) {
+    free(ov);
+    free(bov);
+    free(active);
+    return -1;
+  }
+  for (uint32_t t = 0; t < num_frames; ++t) {
+    const uint32_t* frame = frames + (size_t)t * W;
+    /* B1: boosted overlaps, then the global inhibition on them */
+    spo_overlap(cfg, idx, perm, frame, ov);
+    for (uint32_t c = 0; c < C; ++c) bov[c] = ov[c] * (int32_t)boost[c];
+    spo_inhibit(cfg, bov, active, winners + (size_t)t * k);
+    if (overlaps) memcpy(overlaps + (size_t)t * C, bov, sizeof(int32_t) * C);
+    if (!learn) continue; /* B7 */
+    spo_learn(cfg, idx, perm, frame, active);
+    /* B2: duty cycles */
+    uint32_t max_adc = 0;
+    for (uint32_t c = 0; c < C; ++c) {
+      adc[c] = (uint32_t)(((uint64_t)adc[c] * (P - 1) + (active[c] ? 65536u : 0u)) / P);
+      odc[c] = (uint32_t)(((uint64_t)odc[c] * (P - 1) + (ov[c] > 0 ? 65536u : 0u)) / P);
+      if (adc[c] > max_adc) max_adc = adc[c];
+    }
+    /* B3: the minimum duty cycle */
+    const uint32_t min_dc = (uint32_t)(((uint64_t)max_adc * bc->min_pct_q16) >> 16);
+    for (uint32_t c = 0; c < C; ++c) {
+      /* B4: boost, linear below the minimum */
+      if (min_dc == 0 || adc[c] >= min_dc)
+        boost[c] = 256;
+      else
+        boost[c] = 256 + (uint32_t)(((uint64_t)(bc->max_boost_q8 - 256) * (min_dc - adc[c])) /
+                                    min_dc);
+      /* B5: a column that rarely overlaps gets all its permanences raised */
+      if (odc[c] < min_dc)
+        for (uint32_t s2 = 0; s2 < S; ++s2) {
+          double* p = &perm[(size_t)c * S + s2];
+          *p += bc->bump_q8 / 256.0;
+          if (*p > 1.0) *p = 1.0;
+        }
+    }
+  }
+  free(ov);
+  free(bov);
+  free(active);
+  return 0;
+}

@@ -95,6 +95,41 @@ int spo_run_local(const spo_config* cfg, const uint32_t* idx, double* perm,
                   const uint32_t* frames, uint32_t num_frames, int learn, uint32_t grid_w,
                   uint32_t radius, uint32_t n, int32_t* overlaps, uint8_t* active);
 
+/* Boosting and duty cycles (Algorithm 1 multiplies each gated overlap by the
+ * column's boost, which Section 3.2.2 computes in the kernel; the update
+ * rules are the whitepaper's, spatial pooler phase 3), in exact fixed
+ * point (readings B1-B7 of the design notes):
+ *   B1 boost b[c] in 1/256 units (>= 256); the inhibition ranks the boosted
+ *      overlaps ov[c] * b[c] (R4: global top-k, ties to the lower index);
+ *   B2 duty cycles in 1/65536 units, after each learning frame
+ *      d <- floor((d (P - 1) + 65536 e) / P), P = 2^period_log2, with e = 1
+ *      iff the column won (active duty cycle) or iff its gated overlap is
+ *      positive (overlap duty cycle);
+ *   B3 min duty cycle = floor(max over all columns of the active duty cycle
+ *      * min_pct_q16 / 65536) (global inhibition: every column is a
+ *      neighbour);
+ *   B4 b[c] = 256 if min == 0 or active duty >= min, else
+ *      256 + floor((max_boost_q8 - 256) (min - duty) / min);
+ *   B5 a column whose overlap duty cycle is below the min has every
+ *      permanence raised by bump_q8 / 256, clipped at 1;
+ *   B6 per frame: boosted overlap with the boosts of the previous frame,
+ *      inhibition, learning of the winners, duty cycles, min, boosts, bumps;
+ *   B7 learn = 0 changes nothing (permanences, duty cycles, boosts). */
+typedef struct spo_boost {
+  uint32_t period_log2;  /* P = 2^period_log2, 0..16                       */
+  uint32_t min_pct_q16;  /* min duty cycle as a fraction of the max, /65536 */
+  uint32_t max_boost_q8; /* boost at duty cycle 0, 256..4096                */
+  uint32_t bump_q8;      /* permanence raise on a low overlap duty cycle    */
+} spo_boost;
+
+/* F frames in order with boosting.  adc, odc (duty cycles) and boost
+ * ([C] each) hold the state and are updated in place; overlaps [F][C] (the
+ * boosted overlaps, may be NULL) and winners [F][k] are written.  Returns 0,
+ * -1 on a bad argument. */
+int spo_run_boost(const spo_config* cfg, const spo_boost* bc, const uint32_t* idx, double* perm,
+                  const uint32_t* frames, uint32_t num_frames, int learn, uint32_t* adc,
+                  uint32_t* odc, uint32_t* boost, int32_t* overlaps, int32_t* winners);
+
 /* Per-stream SDR histogram (Section 2: the pooler's output of every frame of
  * a video is accumulated into a histogram that serves as the video's
  * feature vector).  For every frame t < num_frames and every entry

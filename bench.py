@@ -362,6 +362,130 @@ def bench_multi(args, torch, sp, synth):
     return line
 
 
+def bench_encode(args, torch, sp, synth):
+    """The adaptive video encoder on a batch of 960x540 colour frames."""
+    F, W, H = args.encode_frames, 960, 540
+    rgb_h = synth.rgb_frames(synth.rng(14, 6), min(F, 16), W, H)
+    reps = (F + rgb_h.shape[0] - 1) // rgb_h.shape[0]
+    rgb = torch.from_numpy(np.concatenate([rgb_h] * reps)[:F]).cuda()
+    bits = sp.sp_encoded_bits(W, H, args.encode_factor)
+    out = torch.empty((F, (bits + 31) // 32), dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def run(ev0=None, ev1=None):
+        if ev0 is not None:
+            ev0.record(stream)
+        sp.sp_encode(rgb, args.encode_factor, 11, 2, out=out, stream=stream)
+        if ev1 is not None:
+            ev1.record(stream)
+
+    for _ in range(args.warmup):
+        run()
+    torch.cuda.synchronize()
+    warm_clock(lambda: (run(), torch.cuda.synchronize()), args.warm_seconds)
+    wall_s, call_ms = timed(run, args.steps)
+    torch.cuda.synchronize()
+    fps = args.steps * F / wall_s
+    abytes = F * (W * H * 3 + out.shape[1] * 4)
+    achieved = abytes / (call_ms * 1e-3) / 1e9
+    traffic, traffic_bytes = measured_traffic(
+        f"k_encode_960x540_f{args.encode_factor}.md", "k_encode", call_ms)
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        n, dt = 1, 0.0
+        while True:
+            t0 = time.perf_counter()
+            oracle.enc_frames(rgb_h[:n], args.encode_factor, 11, 2)
+            dt = time.perf_counter() - t0
+            if dt > args.cpu_budget / 3 or n >= rgb_h.shape[0]:
+                break
+            n = min(2 * n, rgb_h.shape[0])
+        cpu = {"value": n / dt, "unit": "frames/s", "cores": 1, "kind": "oracle",
+               "sample": f"first {n} of the frames, {dt:.2f} s single-threaded"}
+    return {
+        "metric": "adaptive video encoder frames/s (960x540 RGB to packed SP input)",
+        "value": fps, "unit": "frames/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall_s / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": f"{F} synthetic 960x540 RGB frames per step, reduction factor "
+                               f"{args.encode_factor}, 11x11 binomial window, offset 2",
+                   "frames_per_step": F, "path": "encode"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_encode",
+                     "kernel_ms_per_launch": call_ms, "algorithmic_bytes_per_launch": abytes,
+                     "counter_bytes_per_launch": traffic_bytes},
+        "cpu_baseline": cpu,
+    }
+
+
+def bench_local(args, torch, sp, synth):
+    """Learning with local inhibition (Algorithm 2 with the paper's initial
+    inhibition radius 80 over a 1-D column line): 960x540 blob frames, 1024
+    columns x 256 synapses, n = 6 per neighbourhood (about the 40-in-1024
+    density of the global step)."""
+    F = args.local_frames
+    w = synth.workload_paper_scale(frames=F, columns=1024, synapses=256)
+    cfg = dict(w.cfg)
+    cfg["winners"] = 6
+    C, S = cfg["num_columns"], cfg["synapses_per_column"]
+    pool = sp.SpatialPooler(cfg, w.idx, w.perm)
+    perm0 = pool.perm.clone()
+    frames = torch.from_numpy(w.frames.view(np.int32)).cuda()
+    act = torch.empty((F, C), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def run(ev0=None, ev1=None):
+        pool.perm.copy_(perm0)
+        if ev0 is not None:
+            ev0.record(stream)
+        sp.sp_step_local(pool.handle, cfg, frames, True, 1024, 80, None, act, stream)
+        if ev1 is not None:
+            ev1.record(stream)
+
+    for _ in range(args.warmup):
+        run()
+    pool.sync()
+    warm_clock(lambda: (run(), pool.sync()), args.warm_seconds)
+    wall_s, call_ms = timed(run, args.steps)
+    pool.sync()
+    fps = args.steps * F / wall_s
+    n_act = int(act.sum().item())
+    abytes = F * (frame_bytes(cfg) + 8 * C * S + 4 * C + C) + 12 * S * n_act
+    achieved = abytes / (call_ms * 1e-3) / 1e9
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        n, dt = 8, 0.0
+        while True:
+            t0 = time.perf_counter()
+            oracle.run_local(cfg, w.idx, w.perm, w.frames[:n], 1024, 80, 6, want_overlaps=False)
+            dt = time.perf_counter() - t0
+            if dt > args.cpu_budget / 3 or n >= F:
+                break
+            n = min(2 * n, F)
+        cpu = {"value": n / dt, "unit": "frames/s", "cores": 1, "kind": "oracle",
+               "sample": f"first {n} frames from the same state, {dt:.2f} s single-threaded"}
+    return {
+        "metric": "SP frames/s with local inhibition (radius 80, 1024 columns x 256 synapses, "
+                  "learning on)",
+        "value": fps, "unit": "frames/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall_s / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": f"960x540 blob frames, 1024 columns in a line, radius 80, n = 6 "
+                               f"per neighbourhood, {F} sequential learning frames per step",
+                   "frames_per_step": F, "active_per_frame": n_act / F, "path": "local"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_overlap_plain + k_inhibit_local + k_learn_active",
+                     "kernel_ms_per_launch": call_ms, "algorithmic_bytes_per_launch": abytes,
+                     "counter_bytes_per_launch": None},
+        "cpu_baseline": cpu,
+    }
+
+
 def bench_serve(args, torch, sp, synth):
     from paper_1608_01966_amd import serve
     P = args.pool_frames
@@ -423,7 +547,12 @@ def bench_serve(args, torch, sp, synth):
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["learn", "infer", "multi", "serve"], default="learn")
+    ap.add_argument("--workload",
+                    choices=["learn", "infer", "multi", "serve", "encode", "local"],
+                    default="learn")
+    ap.add_argument("--local-frames", type=int, default=200)
+    ap.add_argument("--encode-frames", type=int, default=256)
+    ap.add_argument("--encode-factor", type=int, default=1)
     ap.add_argument("--streams", type=int, default=256)
     ap.add_argument("--fps", type=float, default=30.0)
     ap.add_argument("--window", type=float, default=10.0)
@@ -469,7 +598,7 @@ def main() -> int:
         del src, dst
 
     fn = {"learn": bench_learn, "infer": bench_infer, "multi": bench_multi,
-          "serve": bench_serve}[args.workload]
+          "serve": bench_serve, "encode": bench_encode, "local": bench_local}[args.workload]
     line = fn(args, torch, sp, synth)
     print(json.dumps(line), flush=True)
     return 0

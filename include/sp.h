@@ -160,6 +160,97 @@ int sp_step_many(sp_handle* const* hs, uint32_t n, const uint32_t* const* frames
                  const uint32_t* num_frames, int learn, int32_t* const* overlaps_dev,
                  int32_t* const* winners_dev, void* stream);
 
+/* Boosting and duty cycles: Algorithm 1 multiplies each column's gated
+ * overlap by its boost (Section 3.2.2 computes it in the kernel); after each
+ * learning frame the duty cycles, the boosts and the permanence raise follow
+ * the whitepaper's spatial pooler phase 3, in exact fixed point:
+ *   boosts in 1/256 (>= 1), duty cycles in 1/65536, each updated as
+ *   d <- floor((d (P - 1) + 65536 e) / P), P = 2^period_log2, e = 1 when
+ *   the column won (active duty cycle) / had a positive gated overlap
+ *   (overlap duty cycle);
+ *   min duty = floor(max active duty * min_pct_q16 / 65536);
+ *   boost = 1 when min == 0 or active duty >= min, else
+ *   1 + floor((max_boost_q8 - 256) (min - duty) / min) / 256;
+ *   a column whose overlap duty cycle is below min has every permanence
+ *   raised by bump_q8 / 256, clipped at 1. */
+typedef struct sp_boost_config {
+  uint32_t period_log2;  /* 0..16                                         */
+  uint32_t min_pct_q16;  /* 0..65536 (655 ~ 0.01)                         */
+  uint32_t max_boost_q8; /* 256..4096                                     */
+  uint32_t bump_q8;      /* 0..256                                        */
+} sp_boost_config;
+
+/* Frames in order with boosting: boosted overlap, global top-k of the
+ * boosted overlaps (ties to the lower index), and with learn != 0 the
+ * winners' learning and the duty-cycle/boost/raise update; one launch
+ * sequence per frame.  The boost state lives in the handle (allocated on
+ * first use, duty cycles 0 and boosts 1) and carries over between calls;
+ * learn = 0 leaves it and the permanences unchanged.  overlaps_dev, if not
+ * NULL, receives the boosted overlaps in 1/256 units. */
+int sp_step_boost(sp_handle* h, const sp_boost_config* cfg, const uint32_t* frames_dev,
+                  uint32_t num_frames, int learn, int32_t* overlaps_dev, int32_t* winners_dev,
+                  void* stream);
+
+/* Copies the boost state (uint32 [C] each; NULL skips one) on `stream`. */
+int sp_boost_state(sp_handle* h, uint32_t* active_duty_dev, uint32_t* overlap_duty_dev,
+                   uint32_t* boost_dev, void* stream);
+
+/* Duty cycles back to 0 and boosts to 1. */
+int sp_boost_reset(sp_handle* h, void* stream);
+
+/* Local inhibition, Algorithm 2 as printed: every column competes within
+ * the neighbourhood an inhibition radius gives it (Section 3.2.2), instead
+ * of the global top-k of sp_step.  Columns sit on a row-major grid of grid_w
+ * columns per row; the neighbourhood of c is every other column whose row
+ * and column coordinates differ from c's by at most `radius` (no wrap); with
+ * v the n-th largest neighbour overlap (0 if there are fewer than n
+ * neighbours), c is active iff overlap[c] > max(v, 1).  Ties at v lose, so
+ * the number of active columns is not fixed.
+ * overlaps_dev: int32 [num_frames][num_columns] gated overlaps (as sp_step or
+ * sp_infer write them); active_dev: uint8 [num_frames][num_columns], 0 or 1.
+ * 1 <= grid_w <= num_columns, n >= 1.  Asynchronous; allocates nothing. */
+int sp_inhibit_local(const int32_t* overlaps_dev, uint32_t num_frames, uint32_t num_columns,
+                     uint32_t grid_w, uint32_t radius, uint32_t n, uint8_t* active_dev,
+                     void* stream);
+
+/* Frames in order through overlap (Algorithm 1), local inhibition (as
+ * sp_inhibit_local, n = the handle's `winners`) and, when learn != 0,
+ * learning on the active columns; one launch sequence per frame.
+ * overlaps_dev [F][C] may be NULL; active_dev is [F][C] uint8.  The
+ * handle's histogram, if set, is not updated by this call. */
+int sp_step_local(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames, int learn,
+                  uint32_t grid_w, uint32_t radius, int32_t* overlaps_dev, uint8_t* active_dev,
+                  void* stream);
+
+/* Adaptive video encoder (Section 3.1.2): colour frames to the pooler's
+ * packed binary input.  Each frame may be reduced by an integer factor
+ * (block means, rounded half up), is converted to grayscale (BT.601 luma in
+ * 14-bit fixed point) and binarised against its neighbourhood: a pixel is
+ * on iff its gray value exceeds the Gaussian-weighted mean of the block x
+ * block window around it minus `offset`, with the binomial weights
+ * C(block - 1, i) as the Gaussian window, edge pixels repeated outside the
+ * image, and the mean rounded half up. */
+typedef struct sp_encoder_config {
+  uint32_t width, height; /* input frame size in pixels                        */
+  uint32_t factor;        /* reduction factor >= 1 (1 = none); output is        */
+                          /* (width / factor) x (height / factor), at most 4096 */
+                          /* pixels wide                                        */
+  uint32_t block;         /* odd window size, 3..11                             */
+  int32_t offset;         /* subtracted from the weighted mean, -255..255       */
+} sp_encoder_config;
+
+/* Input bits of one encoded frame: (width / factor) * (height / factor); 0
+ * on a bad configuration. */
+size_t sp_encoded_bits(const sp_encoder_config* cfg);
+
+/* Encodes num_frames frames.  rgb_dev: device bytes [num_frames][height]
+ * [width][3] (R, G, B).  frames_dev: device words [num_frames][ceil(bits /
+ * 32)] in the layout sp_step reads (pixel p = y w + x at bit p & 31 of word
+ * p >> 5, trailing bits zero).  Asynchronous on `stream`; allocates nothing.
+ * SP_EINVAL on a bad configuration or pointer. */
+int sp_encode(const sp_encoder_config* cfg, const uint8_t* rgb_dev, uint32_t num_frames,
+              uint32_t* frames_dev, void* stream);
+
 /* Per-stream SDR histogram (Section 2: the pooler output of every frame of a
  * video is accumulated into a histogram, the video's feature vector).
  * hist_dev: caller-owned uint32 [num_columns] device buffer, or NULL to stop.

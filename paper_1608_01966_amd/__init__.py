@@ -19,14 +19,16 @@ import ctypes
 
 import numpy as np
 
-from . import synth
+from . import _native, synth
 from ._native import (SP_EBROKEN, SP_EDEVICE, SP_EINVAL, SP_ENOMEM, SP_INFER_GATHER, SP_OK,
                       SpConfig, lib)
 
 __all__ = [
     "SpError", "SpatialPooler", "synth", "sp_config_check", "sp_frame_words",
     "sp_workspace_bytes", "sp_check_state_host", "sp_create", "sp_check_state", "sp_step",
-    "sp_step_plain", "sp_infer", "sp_step_many", "sp_set_histogram", "sp_step_is_persistent",
+    "sp_step_plain", "sp_infer", "sp_step_many", "sp_set_histogram", "sp_encode",
+    "sp_inhibit_local", "sp_step_local", "sp_step_boost", "sp_boost_state", "sp_boost_reset",
+    "sp_encoded_bits", "sp_step_is_persistent",
     "sp_sync",
     "sp_destroy",
     "sp_last_error", "SP_OK", "SP_EINVAL", "SP_ENOMEM", "SP_EDEVICE", "SP_EBROKEN",
@@ -175,6 +177,97 @@ def sp_step_many(handles, cfgs, frames, learn: bool, overlaps, winners, stream=N
         WN[i] = _dev(winners[i], torch.int32, (F, c.winners), f"winners[{i}]")
     _check(lib().sp_step_many(H, n, FR, NF, int(bool(learn)), OV, WN, _stream(stream)),
            "sp_step_many")
+
+
+def _boost_cfg(b: dict):
+    return _native.BoostCfg(int(b["period_log2"]), int(b["min_pct_q16"]),
+                            int(b["max_boost_q8"]), int(b["bump_q8"]))
+
+
+def sp_step_boost(h: int, cfg: dict, bcfg: dict, frames, learn: bool, overlaps, winners,
+                  stream=None) -> None:
+    """Frames in order with boosting; bcfg has period_log2, min_pct_q16,
+    max_boost_q8, bump_q8; overlaps (boosted, may be None) and winners are
+    GPU tensors [F][C] and [F][k]."""
+    b = _boost_cfg(bcfg)
+    _check(lib().sp_step_boost(ctypes.c_void_p(h), ctypes.byref(b),
+                               ctypes.c_void_p(frames.data_ptr()), int(frames.shape[0]),
+                               int(bool(learn)),
+                               ctypes.c_void_p(overlaps.data_ptr()) if overlaps is not None
+                               else None, ctypes.c_void_p(winners.data_ptr()), _stream(stream)),
+           "sp_step_boost")
+
+
+def sp_boost_state(h: int, num_columns: int, stream=None):
+    """(active duty, overlap duty, boost) as int32 GPU tensors [C]."""
+    import torch
+    out = [torch.empty(num_columns, dtype=torch.int32, device="cuda") for _ in range(3)]
+    _check(lib().sp_boost_state(ctypes.c_void_p(h), *(ctypes.c_void_p(t.data_ptr()) for t in out),
+                                _stream(stream)), "sp_boost_state")
+    return tuple(out)
+
+
+def sp_boost_reset(h: int, stream=None) -> None:
+    _check(lib().sp_boost_reset(ctypes.c_void_p(h), _stream(stream)), "sp_boost_reset")
+
+
+def sp_inhibit_local(overlaps, grid_w: int, radius: int, n: int, active=None, stream=None):
+    """overlaps: int32 GPU tensor [F][C].  Returns (or fills) the uint8 GPU
+    tensor [F][C] of active flags (Algorithm 2 with a neighbourhood)."""
+    import torch
+    assert overlaps.is_cuda and overlaps.dtype == torch.int32 and overlaps.dim() == 2
+    overlaps = overlaps.contiguous()
+    F, C = (int(x) for x in overlaps.shape)
+    if active is None:
+        active = torch.empty((F, C), dtype=torch.uint8, device=overlaps.device)
+    assert active.is_contiguous() and active.shape == (F, C) and active.dtype == torch.uint8
+    _check(lib().sp_inhibit_local(ctypes.c_void_p(overlaps.data_ptr()), F, C, int(grid_w),
+                                  int(radius), int(n), ctypes.c_void_p(active.data_ptr()),
+                                  _stream(stream)), "sp_inhibit_local")
+    return active
+
+
+def sp_step_local(h: int, cfg: dict, frames, learn: bool, grid_w: int, radius: int,
+                  overlaps, active, stream=None) -> None:
+    """Frames in order with local inhibition (n = cfg winners); overlaps may
+    be None; active: uint8 GPU tensor [F][C]."""
+    F = int(frames.shape[0])
+    assert active.shape == (F, cfg["num_columns"])
+    _check(lib().sp_step_local(ctypes.c_void_p(h), ctypes.c_void_p(frames.data_ptr()), F,
+                               int(bool(learn)), int(grid_w), int(radius),
+                               ctypes.c_void_p(overlaps.data_ptr()) if overlaps is not None
+                               else None, ctypes.c_void_p(active.data_ptr()),
+                               _stream(stream)), "sp_step_local")
+
+
+def _enc_cfg(width: int, height: int, factor: int = 1, block: int = 11, offset: int = 2):
+    return _native.EncCfg(int(width), int(height), int(factor), int(block), int(offset))
+
+
+def sp_encoded_bits(width: int, height: int, factor: int = 1, block: int = 11,
+                    offset: int = 2) -> int:
+    """Input bits of one encoded frame (0 for a bad configuration)."""
+    return int(lib().sp_encoded_bits(ctypes.byref(_enc_cfg(width, height, factor, block,
+                                                           offset))))
+
+
+def sp_encode(rgb, factor: int = 1, block: int = 11, offset: int = 2, out=None, stream=None):
+    """rgb: uint8 GPU tensor [F][H][W][3].  Returns (or fills) the int32 GPU
+    tensor [F][ceil(bits / 32)] of packed binary frames."""
+    import torch
+    assert rgb.is_cuda and rgb.dtype == torch.uint8 and rgb.dim() == 4 and rgb.shape[3] == 3
+    rgb = rgb.contiguous()
+    F, H, W = (int(x) for x in rgb.shape[:3])
+    c = _enc_cfg(W, H, factor, block, offset)
+    bits = int(lib().sp_encoded_bits(ctypes.byref(c)))
+    if bits == 0:
+        raise SpError(SP_EINVAL, f"sp_encoded_bits: {sp_last_error()}")
+    if out is None:
+        out = torch.empty((F, (bits + 31) // 32), dtype=torch.int32, device=rgb.device)
+    assert out.is_contiguous() and out.shape == (F, (bits + 31) // 32)
+    _check(lib().sp_encode(ctypes.byref(c), ctypes.c_void_p(rgb.data_ptr()), F,
+                           ctypes.c_void_p(out.data_ptr()), _stream(stream)), "sp_encode")
+    return out
 
 
 def sp_set_histogram(h: int, hist=None) -> None:

@@ -35,6 +35,27 @@ class SpConfig(ctypes.Structure):
 
 
 # (name, restype, argtypes) for every function include/sp.h declares.
+class EncCfg(ctypes.Structure):
+    """sp_encoder_config of include/sp.h."""
+    _fields_ = [
+        ("width", ctypes.c_uint32),
+        ("height", ctypes.c_uint32),
+        ("factor", ctypes.c_uint32),
+        ("block", ctypes.c_uint32),
+        ("offset", ctypes.c_int32),
+    ]
+
+
+class BoostCfg(ctypes.Structure):
+    """sp_boost_config of include/sp.h."""
+    _fields_ = [
+        ("period_log2", ctypes.c_uint32),
+        ("min_pct_q16", ctypes.c_uint32),
+        ("max_boost_q8", ctypes.c_uint32),
+        ("bump_q8", ctypes.c_uint32),
+    ]
+
+
 P = ctypes.c_void_p
 CFG = ctypes.POINTER(SpConfig)
 U32 = ctypes.c_uint32
@@ -50,6 +71,14 @@ SIGNATURES = [
     ("sp_infer", ctypes.c_int, [P, P, U32, ctypes.c_int, P, P, P]),
     ("sp_step_many", ctypes.c_int, [P, U32, P, P, ctypes.c_int, P, P, P]),
     ("sp_set_histogram", ctypes.c_int, [P, P]),
+    ("sp_step_boost", ctypes.c_int, [P, ctypes.POINTER(BoostCfg), P, U32, ctypes.c_int, P, P,
+                                     P]),
+    ("sp_boost_state", ctypes.c_int, [P, P, P, P, P]),
+    ("sp_boost_reset", ctypes.c_int, [P, P]),
+    ("sp_inhibit_local", ctypes.c_int, [P, U32, U32, U32, U32, U32, P, P]),
+    ("sp_step_local", ctypes.c_int, [P, P, U32, ctypes.c_int, U32, U32, P, P, P]),
+    ("sp_encoded_bits", ctypes.c_size_t, [ctypes.POINTER(EncCfg)]),
+    ("sp_encode", ctypes.c_int, [ctypes.POINTER(EncCfg), P, U32, P, P]),
     ("sp_step_is_persistent", ctypes.c_int, [P]),
     ("sp_sync", ctypes.c_int, [P, P]),
     ("sp_destroy", ctypes.c_int, [P]),

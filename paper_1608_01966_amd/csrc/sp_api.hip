@@ -32,6 +32,8 @@ struct sp_handle {
   int32_t* ov_scratch; // [C]
   uint32_t* many_ovx;  // [C] tagged overlaps of the many-instance step
   uint32_t* hist;      // caller's [C] winner counts, or null
+  uint32_t* boost_mem; // [3][C] active duty, overlap duty, boost, then [C] raise flags
+  uint32_t boost_C;    // columns the boost state was set up for (0: none yet)
   uint64_t* many_dec;  // decision word of the many-instance step
   uint32_t many_steps; // steps this handle has taken through sp_step_many
   uint64_t xchg_frames;
@@ -197,19 +199,26 @@ void plan_persistent(sp_handle* h) {
     return;
   const uint32_t rpc = next_pow2((sh.S + 63) / 64);
   const uint32_t nv = next_pow2(htmsp::persistent_exchange_entries(sh.C) / 256);
-  const void* k = htmsp::persistent_kernel(rpc, nv);
-  if (!k) return;
-  const uint32_t cpw = htmsp::persistent_rows() / rpc;
-  const uint32_t grid = (sh.C + cpw - 1) / cpw;
-  const size_t lds = htmsp::persistent_lds_bytes();
-  int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 128, lds) != hipSuccess) return;
-  if ((uint64_t)per_cu * (uint64_t)cus < grid) return;
-  h->grid = grid;
-  h->replicas = htmsp::kPersistReplicas;
-  h->pkernel = k;
-  h->plds = lds;
-  h->persistent = true;
+  // The fewest rows per workgroup (most workgroups) whose grid is
+  // co-resident, else 16.
+  const uint32_t small = std::max(rpc, htmsp::kPersistMinRows);
+  for (uint32_t rows : {small, 16u}) {
+    if (rows < small) continue;
+    const void* k = htmsp::persistent_kernel(rpc, nv, rows);
+    if (!k) continue;
+    const uint32_t cpw = rows / rpc;
+    const uint32_t grid = (sh.C + cpw - 1) / cpw;
+    const size_t lds = htmsp::persistent_lds_bytes(rows);
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 128, lds) != hipSuccess) return;
+    if ((uint64_t)per_cu * (uint64_t)cus < grid) continue;
+    h->grid = grid;
+    h->replicas = htmsp::kPersistReplicas;
+    h->pkernel = k;
+    h->plds = lds;
+    h->persistent = true;
+    return;
+  }
 }
 
 int run_check_state(sp_handle* h, hipStream_t s) {
@@ -289,8 +298,8 @@ int many_slot(int device, size_t bytes, ManySlot** out) {
 // tiles (tiles <= kMaxTileSlots * maxb).
 int many_launch(sp_handle* const* hs, uint32_t n, const uint32_t* const* frames_dev,
                 const uint32_t* num_frames, int learn, int32_t* const* overlaps_dev,
-                int32_t* const* winners_dev, hipStream_t s, int dev, int maxb, size_t ntiles,
-                uint32_t nact, uint32_t Fmax, uint32_t* err) {
+                int32_t* const* winners_dev, hipStream_t s, int dev, int maxb, bool aligned,
+                size_t ntiles, uint32_t nact, uint32_t Fmax, uint32_t* err) {
   const uint32_t ntasks = (uint32_t)(ntiles + nact);
   const uint32_t grid = std::min<uint32_t>(ntasks, (uint32_t)maxb);
   std::vector<std::vector<htmsp::ManyTask>> per(grid);
@@ -314,6 +323,7 @@ int many_launch(sp_handle* const* hs, uint32_t n, const uint32_t* const* frames_
     in.F = num_frames[i];
     in.step_base = h->many_steps;
     in.guess = 1 + h->sh.S / 16;
+    in.smagic = h->sh.S == 1 ? 0u : (uint32_t)(((1ull << 32) + h->sh.S - 1) / h->sh.S);
     insts.push_back(in);
     const uint32_t ct = htmsp::many_tile_columns(h->sh.S);
     for (uint32_t c0 = 0; c0 < h->sh.C; c0 += ct)
@@ -349,7 +359,7 @@ int many_launch(sp_handle* const* hs, uint32_t n, const uint32_t* const* frames_
   a.Fmax = Fmax;
   a.learn = learn ? 1u : 0u;
   a.spin_limit = kSpinLimit;
-  e = htmsp::launch_many(a, grid, s);
+  e = htmsp::launch_many(a, grid, aligned, s);
   if (e == hipSuccess) e = hipEventRecord(sl->done, s);
   if (e != hipSuccess) return hip_fail(e, "many-instance launch");
   return SP_OK;
@@ -595,7 +605,9 @@ int sp_step_many(sp_handle* const* hs, uint32_t n, const uint32_t* const* frames
   if (nact == 0) return ok();
   DeviceScope ds(dev);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const int maxb = htmsp::many_max_blocks(dev);
+  bool aligned = true;
+  for (uint32_t i = 0; i < n; ++i) aligned = aligned && hs[i]->sh.S % 64 == 0;
+  const int maxb = htmsp::many_max_blocks(dev, aligned);
   if (maxb <= 0) return fail(SP_EDEVICE, "cannot size the many-instance launch");
   // Instances are independent, so they may be split over consecutive
   // launches: each launch holds at most kMaxTileSlots tiles per workgroup.
@@ -625,7 +637,7 @@ int sp_step_many(sp_handle* const* hs, uint32_t n, const uint32_t* const* frames
     if (nact_c > 0) {
       int rc = many_launch(hs + i0, i1 - i0, frames_dev + i0, num_frames + i0, learn,
                            overlaps_dev ? overlaps_dev + i0 : nullptr, winners_dev + i0, s, dev,
-                           maxb, tiles_c, nact_c, Fmax_c, hs[0]->err);
+                           maxb, aligned, tiles_c, nact_c, Fmax_c, hs[0]->err);
       if (rc) return rc;
     }
     i0 = i1;
@@ -635,6 +647,226 @@ int sp_step_many(sp_handle* const* hs, uint32_t n, const uint32_t* const* frames
     hs[i]->many_steps += num_frames[i];
     if (learn) ++hs[i]->state_version;
   }
+  return ok();
+}
+
+}  // extern "C"
+
+namespace {
+
+// Tile of about 8 output rows (fewer for wide frames), a multiple of 64
+// pixels, whose LDS (gray rows with halo, vertical sums) fits 64 KB so that
+// two workgroups share a CU; 0 when even one row does not fit.
+int encoder_shape(const sp_encoder_config* c, htmsp::EncShape* e) {
+  if (!c) return fail(SP_EINVAL, "encoder config is NULL");
+  if (c->factor < 1) return fail(SP_EINVAL, "factor must be >= 1");
+  if (c->block < 3 || c->block > 11 || c->block % 2 == 0)
+    return fail(SP_EINVAL, "block=%u must be odd in 3..11", c->block);
+  if (c->offset < -255 || c->offset > 255)
+    return fail(SP_EINVAL, "offset=%d outside -255..255", c->offset);
+  const uint32_t w = c->width / c->factor, h = c->height / c->factor;
+  if (w < 1 || h < 1) return fail(SP_EINVAL, "frame smaller than the reduction factor");
+  if (w > 4096) return fail(SP_EINVAL, "encoded width %u > 4096", w);
+  if ((uint64_t)w * h > SP_MAX_INPUT_BITS)
+    return fail(SP_EINVAL, "encoded frame has %llu bits > %u", (unsigned long long)w * h,
+                SP_MAX_INPUT_BITS);
+  e->W = c->width;
+  e->H = c->height;
+  e->factor = c->factor;
+  e->block = c->block;
+  e->offset = c->offset;
+  e->w = w;
+  e->h = h;
+  e->words = (uint32_t)(((uint64_t)w * h + 31) / 32);
+  const uint32_t r = c->block / 2;
+  for (uint32_t rows : {8u, 4u, 2u, 1u}) {
+    const uint32_t tile = std::max<uint32_t>(64u, rows * w / 64 * 64);
+    const uint32_t vrows = (tile + w - 1) / w + 1, grows = vrows + 2 * r;
+    const uint32_t gray = (uint32_t)align_up((size_t)grows * w, 4);
+    const uint32_t lds = gray + vrows * w * 4;
+    if (lds <= 65536 || rows == 1) {
+      if (lds > 160 * 1024) return fail(SP_EINVAL, "encoded width %u too large", w);
+      e->tile_px = tile;
+      e->tiles = (uint32_t)(((uint64_t)w * h + tile - 1) / tile);
+      e->gray_bytes = gray;
+      e->lds_bytes = lds;
+      return SP_OK;
+    }
+  }
+  return fail(SP_EINVAL, "encoder tiling failed");
+}
+
+}  // namespace
+
+extern "C" {
+
+int sp_inhibit_local(const int32_t* overlaps_dev, uint32_t num_frames, uint32_t num_columns,
+                     uint32_t grid_w, uint32_t radius, uint32_t n, uint8_t* active_dev,
+                     void* stream) {
+  if (num_columns < 1 || num_columns > SP_MAX_COLUMNS)
+    return fail(SP_EINVAL, "num_columns=%u outside 1..%u", num_columns, SP_MAX_COLUMNS);
+  if (grid_w < 1 || grid_w > num_columns)
+    return fail(SP_EINVAL, "grid_w=%u outside 1..num_columns", grid_w);
+  if (n < 1) return fail(SP_EINVAL, "n must be >= 1");
+  if (num_frames == 0) return ok();
+  if (!overlaps_dev || !active_dev || !aligned4(overlaps_dev))
+    return fail(SP_EINVAL, "overlaps (4-byte aligned) and active are required");
+  hipError_t e = htmsp::launch_inhibit_local(overlaps_dev, num_frames, num_columns, grid_w,
+                                             radius, n, active_dev,
+                                             static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "local inhibition launch");
+  return ok();
+}
+
+int sp_step_local(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames, int learn,
+                  uint32_t grid_w, uint32_t radius, int32_t* overlaps_dev, uint8_t* active_dev,
+                  void* stream) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  const Shape& sh = h->sh;
+  if (grid_w < 1 || grid_w > sh.C) return fail(SP_EINVAL, "grid_w=%u outside 1..C", grid_w);
+  if (num_frames == 0) return ok();
+  if (!frames_dev || !active_dev || !aligned4(frames_dev) || (overlaps_dev && !aligned4(overlaps_dev)))
+    return fail(SP_EINVAL, "frames (4-byte aligned) and active are required");
+  DeviceScope ds(h->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (learn) ++h->state_version;
+  for (uint32_t t = 0; t < num_frames; ++t) {
+    const uint32_t* frame = frames_dev + (size_t)t * sh.W;
+    int32_t* ov = overlaps_dev ? overlaps_dev + (size_t)t * sh.C : h->ov_scratch;
+    uint8_t* act = active_dev + (size_t)t * sh.C;
+    hipError_t e = htmsp::launch_overlap_plain(h->idx, h->perm, frame, ov, sh, s);
+    if (e == hipSuccess)
+      e = htmsp::launch_inhibit_local(ov, 1, sh.C, grid_w, radius, sh.k, act, s);
+    if (e == hipSuccess && learn) e = htmsp::launch_learn_active(h->idx, h->perm, frame, act, sh, s);
+    if (e != hipSuccess) return hip_fail(e, "local step launch");
+  }
+  return ok();
+}
+
+}  // extern "C"
+
+namespace {
+
+int check_boost(const sp_boost_config* b, uint32_t S) {
+  if (!b) return fail(SP_EINVAL, "boost config is NULL");
+  if (b->period_log2 > 16) return fail(SP_EINVAL, "period_log2=%u > 16", b->period_log2);
+  if (b->min_pct_q16 > 65536) return fail(SP_EINVAL, "min_pct_q16=%u > 65536", b->min_pct_q16);
+  if (b->max_boost_q8 < 256 || b->max_boost_q8 > 4096)
+    return fail(SP_EINVAL, "max_boost_q8=%u outside 256..4096", b->max_boost_q8);
+  if (b->bump_q8 > 256) return fail(SP_EINVAL, "bump_q8=%u > 256", b->bump_q8);
+  (void)S;
+  return SP_OK;
+}
+
+// Boost state on the device, set to duty cycles 0 and boosts 1 on first use.
+int ensure_boost(sp_handle* h, hipStream_t s) {
+  if (h->boost_mem) return SP_OK;
+  const uint32_t C = h->sh.C;
+  const size_t bytes = sizeof(uint32_t) * 3 * (size_t)C + align_up(C, 4);
+  hipError_t e = hipMalloc(&h->boost_mem, bytes);
+  if (e != hipSuccess) {
+    h->boost_mem = nullptr;
+    return fail(SP_ENOMEM, "boost state hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+  }
+  h->boost_C = C;
+  e = htmsp::launch_boost_init(h->boost_mem, h->boost_mem + C, h->boost_mem + 2 * (size_t)C, C,
+                               s);
+  if (e != hipSuccess) return hip_fail(e, "boost state init");
+  return SP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sp_step_boost(sp_handle* h, const sp_boost_config* bc, const uint32_t* frames_dev,
+                  uint32_t num_frames, int learn, int32_t* overlaps_dev, int32_t* winners_dev,
+                  void* stream) {
+  int rc = check_step_args(h, frames_dev, num_frames, overlaps_dev, winners_dev);
+  if (rc) return rc;
+  rc = check_boost(bc, h->sh.S);
+  if (rc) return rc;
+  if (num_frames == 0) return ok();
+  DeviceScope ds(h->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  rc = ensure_boost(h, s);
+  if (rc) return rc;
+  const Shape& sh = h->sh;
+  uint32_t* adc = h->boost_mem;
+  uint32_t* odc = adc + sh.C;
+  uint32_t* boost = odc + sh.C;
+  uint8_t* raise = reinterpret_cast<uint8_t*>(boost + sh.C);
+  const htmsp::BoostParams bp = {bc->period_log2, bc->min_pct_q16, bc->max_boost_q8,
+                                 bc->bump_q8};
+  if (learn) ++h->state_version;
+  for (uint32_t t = 0; t < num_frames; ++t) {
+    const uint32_t* frame = frames_dev + (size_t)t * sh.W;
+    int32_t* ov = overlaps_dev ? overlaps_dev + (size_t)t * sh.C : h->ov_scratch;
+    int32_t* win = winners_dev + (size_t)t * sh.k;
+    hipError_t e = htmsp::launch_overlap_plain(h->idx, h->perm, frame, ov, sh, s, boost);
+    if (e == hipSuccess) e = htmsp::launch_topk_plain(ov, win, sh, s, 1, sh.S * bc->max_boost_q8);
+    if (learn) {
+      if (e == hipSuccess) e = htmsp::launch_learn_plain(h->idx, h->perm, frame, win, sh, s);
+      if (e == hipSuccess)
+        e = htmsp::launch_boost_update(ov, win, sh, bp, adc, odc, boost, raise, h->perm, s);
+    }
+    if (e != hipSuccess) return hip_fail(e, "boosted step launch");
+  }
+  return add_histogram(h, winners_dev, num_frames, s);
+}
+
+int sp_boost_state(sp_handle* h, uint32_t* active_duty_dev, uint32_t* overlap_duty_dev,
+                   uint32_t* boost_dev, void* stream) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  DeviceScope ds(h->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  rc = ensure_boost(h, s);
+  if (rc) return rc;
+  const size_t n = sizeof(uint32_t) * h->sh.C;
+  hipError_t e = hipSuccess;
+  if (active_duty_dev)
+    e = hipMemcpyAsync(active_duty_dev, h->boost_mem, n, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess && overlap_duty_dev)
+    e = hipMemcpyAsync(overlap_duty_dev, h->boost_mem + h->sh.C, n, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess && boost_dev)
+    e = hipMemcpyAsync(boost_dev, h->boost_mem + 2 * (size_t)h->sh.C, n,
+                       hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "boost state copy");
+  return ok();
+}
+
+int sp_boost_reset(sp_handle* h, void* stream) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (!h->boost_mem) return ok();
+  DeviceScope ds(h->device);
+  hipError_t e = htmsp::launch_boost_init(h->boost_mem, h->boost_mem + h->sh.C,
+                                          h->boost_mem + 2 * (size_t)h->sh.C, h->sh.C,
+                                          static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "boost state reset");
+  return ok();
+}
+
+size_t sp_encoded_bits(const sp_encoder_config* cfg) {
+  htmsp::EncShape e;
+  if (encoder_shape(cfg, &e)) return 0;
+  ok();
+  return (size_t)e.w * e.h;
+}
+
+int sp_encode(const sp_encoder_config* cfg, const uint8_t* rgb_dev, uint32_t num_frames,
+              uint32_t* frames_dev, void* stream) {
+  htmsp::EncShape e;
+  int rc = encoder_shape(cfg, &e);
+  if (rc) return rc;
+  if (num_frames == 0) return ok();
+  if (!rgb_dev || !frames_dev) return fail(SP_EINVAL, "rgb and frames are required");
+  if (!aligned4(frames_dev)) return fail(SP_EINVAL, "frames must be 4-byte aligned");
+  hipError_t err = htmsp::launch_encode(rgb_dev, num_frames, e, frames_dev,
+                                        static_cast<hipStream_t>(stream));
+  if (err != hipSuccess) return hip_fail(err, "encoder launch");
   return ok();
 }
 
@@ -679,6 +911,7 @@ int sp_destroy(sp_handle* h) {
     if (e == hipSuccess) e = hipFree(h->ws);
     if (e == hipSuccess && h->infer_list) e = hipFree(h->infer_list);
     if (e == hipSuccess && h->infer_ov) e = hipFree(h->infer_ov);
+    if (e == hipSuccess && h->boost_mem) e = hipFree(h->boost_mem);
     if (e != hipSuccess) rc = hip_fail(e, "destroy");
   }
   delete h;

@@ -39,26 +39,32 @@ constexpr uint32_t kPersistMaxSynapses = 1024;
 constexpr uint32_t kPersistMaxReplicas = 8;
 constexpr uint32_t kPersistReplicas = 2;
 
-size_t persistent_lds_bytes();
-// Rows of 64 synapses one workgroup holds.
-uint32_t persistent_rows();
+// LDS of one persistent workgroup holding `rows` rows of 64 synapses.
+size_t persistent_lds_bytes(uint32_t rows);
+// Smallest rows per workgroup the persistent kernel is built for (it also
+// exists for 8 rows when rpc = 8 and for 16 rows).
+constexpr uint32_t kPersistMinRows = 4;
 // Exchange arrays per slot (frame t, frame t+1 if lost, frame t+1 if won).
 uint32_t persistent_exchange_arrays();
 // 16-bit exchange entries per array for C columns: 256 times the power of two
 // of 64-bit words per lane that covers C.
 uint32_t persistent_exchange_entries(uint32_t C);
-// The kernel instance for `rpc` rows per column (1, 2, 4, 8 or 16) and `nv`
-// 64-bit exchange words per lane (1, 2, 4, 8 or 16); nullptr otherwise.
-const void* persistent_kernel(uint32_t rpc, uint32_t nv);
+// The kernel instance for `rpc` rows per column (1, 2, 4, 8 or 16), `nv`
+// 64-bit exchange words per lane (1, 2, 4, 8 or 16) and `rows` rows per
+// workgroup (max(rpc, 4) or 16); nullptr otherwise.
+const void* persistent_kernel(uint32_t rpc, uint32_t nv, uint32_t rows);
 
 hipError_t launch_check_state(const uint32_t* idx, const float* perm, size_t n, uint32_t N,
                               uint32_t* out4, hipStream_t s);
+// Gated overlaps of one frame; times boost[c] (1/256 units) when boost is set.
 hipError_t launch_overlap_plain(const uint32_t* idx, const float* perm, const uint32_t* frame,
-                                int32_t* ov, const Shape& sh, hipStream_t s);
+                                int32_t* ov, const Shape& sh, hipStream_t s,
+                                const uint32_t* boost = nullptr);
 // Top-k of `frames` consecutive frames (overlaps [frames][C], winners
 // [frames][k]), one workgroup per frame.
+// Overlaps lie in [0, vmax] (0: S).
 hipError_t launch_topk_plain(const int32_t* ov, int32_t* winners, const Shape& sh, hipStream_t s,
-                             uint32_t frames = 1);
+                             uint32_t frames = 1, uint32_t vmax = 0);
 hipError_t launch_learn_plain(const uint32_t* idx, float* perm, const uint32_t* frame,
                               const int32_t* winners, const Shape& sh, hipStream_t s);
 
@@ -78,13 +84,46 @@ hipError_t launch_infer_gather(uint32_t maxn, const uint32_t* frames, uint32_t F
 hipError_t launch_topk_batch(const int32_t* ov, uint32_t F, const Shape& sh, int32_t* winners,
                              hipStream_t s);
 
+// Adaptive video encoder (sp_encode.hip).  W x H RGB input, w x h output
+// (w = W / factor, h = H / factor), tiles of tile_px output pixels (a
+// multiple of 64), LDS for the gray halo rows and the vertical sums.
+struct EncShape {
+  uint32_t W, H, factor, block;
+  int32_t offset;
+  uint32_t w, h, words;       // output size, words per frame
+  uint32_t tile_px, tiles;    // pixels per tile, tiles per frame
+  uint32_t gray_bytes;        // LDS bytes of the gray rows
+  uint32_t lds_bytes;         // total LDS per workgroup
+};
+hipError_t launch_encode(const uint8_t* rgb, uint32_t F, const EncShape& e, uint32_t* out,
+                         hipStream_t s);
+
+// Boosting and duty cycles (sp_boost.hip), per learning frame after the
+// winners' learning: duty cycles, the minimum, boosts, and the permanence
+// raise of columns whose overlap duty cycle is below the minimum.
+struct BoostParams {
+  uint32_t period_log2, min_pct_q16, max_boost_q8, bump_q8;
+};
+hipError_t launch_boost_update(const int32_t* ov, const int32_t* winners, const Shape& sh,
+                               const BoostParams& b, uint32_t* adc, uint32_t* odc,
+                               uint32_t* boost, uint8_t* raise, float* perm, hipStream_t s);
+hipError_t launch_boost_init(uint32_t* adc, uint32_t* odc, uint32_t* boost, uint32_t C,
+                             hipStream_t s);
+
+// Local inhibition (sp_local.hip): active [F][C] from overlaps [F][C].
+hipError_t launch_inhibit_local(const int32_t* ov, uint32_t F, uint32_t C, uint32_t grid_w,
+                                uint32_t radius, uint32_t n, uint8_t* active, hipStream_t s);
+// Learning of one frame on the columns flagged in active[C].
+hipError_t launch_learn_active(const uint32_t* idx, float* perm, const uint32_t* frame,
+                               const uint8_t* active, const Shape& sh, hipStream_t s);
+
 // Adds 1 to hist[c] for every entry c >= 0 of winners[n] (sp_hist.hip).
 hipError_t launch_hist_add(const int32_t* winners, size_t n, uint32_t C, uint32_t* hist,
                            hipStream_t s);
 
 // Many instances in one persistent launch (sp_many.hip).
 constexpr uint32_t kManyNV = 16;          // top-k words per lane: C <= 4096
-constexpr uint32_t kTileSynapses = 8192;  // synapses per tile task (at most)
+constexpr uint32_t kTileSynapses = 4096;  // synapses per tile task (at most)
 constexpr uint32_t kTileColumns = 1024;   // columns per tile task (at most)
 constexpr uint32_t kManyThreads = 256;
 constexpr uint32_t kMaxTileSlots = 16;    // tile tasks per workgroup (at most)
@@ -99,7 +138,8 @@ struct ManyInst {
   uint64_t* dec;           // decision word
   uint32_t* hist;          // [C] winner counts to add to, or null
   Shape sh;
-  uint32_t F, step_base, guess, pad;
+  uint32_t F, step_base, guess;
+  uint32_t smagic;         // ceil(2^32 / S), 0 for S = 1: floor(p / S) for p < 2^13
 };
 
 struct ManyTask {
@@ -116,8 +156,9 @@ struct ManyArgs {
 
 // Columns of one tile task for S synapses per column.
 uint32_t many_tile_columns(uint32_t S);
-// Co-resident blocks of the many-instance kernel on `device` (0 on error).
-int many_max_blocks(int device);
-hipError_t launch_many(const ManyArgs& a, uint32_t grid, hipStream_t s);
+// Co-resident blocks of the many-instance kernel on `device` (0 on error);
+// `aligned`: the kernel for launches whose instances all have S % 64 == 0.
+int many_max_blocks(int device, bool aligned);
+hipError_t launch_many(const ManyArgs& a, uint32_t grid, bool aligned, hipStream_t s);
 
 }  // namespace htmsp

@@ -43,11 +43,13 @@ __global__ __launch_bounds__(256) void k_check_state(const uint32_t* __restrict_
 }
 
 // ---------------------------------------------------------------------------
-// Plain overlap (Algorithm 1): one wave per column, 64 synapses per ballot.
+// Plain overlap (Algorithm 1): one wave per column, 64 synapses per ballot;
+// with `boost` (1/256 units per column) the gated overlap is multiplied by it.
 __global__ __launch_bounds__(256) void k_overlap_plain(const uint32_t* __restrict__ idx,
                                                        const float* __restrict__ perm,
                                                        const uint32_t* __restrict__ frame,
-                                                       int32_t* __restrict__ ov, Shape sh) {
+                                                       int32_t* __restrict__ ov, Shape sh,
+                                                       const uint32_t* __restrict__ boost) {
   const uint32_t lane = threadIdx.x % kWave;
   const uint32_t c = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
   if (c >= sh.C) return;
@@ -63,11 +65,13 @@ __global__ __launch_bounds__(256) void k_overlap_plain(const uint32_t* __restric
     }
     raw += (uint32_t)__popcll(__ballot(hit));
   }
-  if (lane == 0) ov[c] = raw >= sh.m ? (int32_t)raw : 0;
+  const uint32_t gated = raw >= sh.m ? raw : 0u;
+  if (lane == 0) ov[c] = (int32_t)(boost ? gated * boost[c] : gated);
 }
 
 // ---------------------------------------------------------------------------
 // Plain global top-k (Algorithm 2, global form) in one workgroup of 1024.
+// Overlaps lie in [0, vmax] (S, or S times the largest boost).
 // T = the largest value x >= 1 with #(overlap >= x) >= k (0 if fewer than k
 // overlaps are positive) is found by binary search on block-wide counts;
 // then every column above T wins, and the lowest-index columns equal to T
@@ -105,7 +109,7 @@ __device__ uint32_t block_excl_scan(bool flag, uint32_t* red, uint32_t* total) {
 
 __global__ __launch_bounds__(kTopkThreads) void k_topk_plain(const int32_t* __restrict__ ov,
                                                             int32_t* __restrict__ winners,
-                                                            Shape sh) {
+                                                            Shape sh, uint32_t vmax) {
   __shared__ uint32_t red[kTopkThreads / kWave];
   ov += (size_t)blockIdx.x * sh.C;  // one frame per workgroup
   winners += (size_t)blockIdx.x * sh.k;
@@ -118,7 +122,7 @@ __global__ __launch_bounds__(kTopkThreads) void k_topk_plain(const int32_t* __re
   int32_t T = 0;
   uint32_t need = 0;
   if (count_ge(1) >= sh.k) {
-    int32_t lo = 1, hi = (int32_t)sh.S;
+    int32_t lo = 1, hi = (int32_t)vmax;
     while (lo < hi) {
       const int32_t mid = (lo + hi + 1) / 2;
       if (count_ge(mid) >= sh.k) lo = mid; else hi = mid - 1;
@@ -163,8 +167,11 @@ __global__ __launch_bounds__(256) void k_learn_plain(const uint32_t* __restrict_
 // ---------------------------------------------------------------------------
 // Persistent multi-frame step.
 //
-// Workgroup g (two waves) owns CPW = kRows / RPC consecutive columns from
+// Workgroup g (two waves) owns CPW = ROWS / RPC consecutive columns from
 // g*CPW; row r holds synapses (r % RPC)*64 + lane of local column r / RPC.
+// Fewer rows per workgroup means more workgroups, each with a shorter serial
+// chain of per-frame work; the host picks the smallest ROWS whose grid is
+// co-resident.
 //   wave 0 (main) keeps the synapse state in registers for the whole launch
 //     (idx << 9 | q, plus the mask of the input bit when connected) and, per
 //     frame: overlap of its columns, publish, collect every column's
@@ -181,7 +188,7 @@ __global__ __launch_bounds__(256) void k_learn_plain(const uint32_t* __restrict_
 // belongs to frame g - 2 with tag (g - 1) & 3 (or is the zeroed initial
 // state), so a stale entry is never taken for a fresh one, and a slot is
 // rewritten only after every workgroup has finished reading it.
-constexpr uint32_t kRows = 16;
+constexpr uint32_t kMaxRows = 16;
 constexpr uint32_t kRing = 8;
 
 __device__ __forceinline__ void lds_release(uint32_t* p, uint32_t v) {
@@ -221,9 +228,9 @@ __device__ __forceinline__ uint64_t tag_mask(uint32_t u, uint32_t lane, uint32_t
 
 // Own columns: overlaps of this group's columns for one frame (Algorithm 1,
 // gated at min_overlap), as wave-uniform values.
-template <int RPC, int CPW>
-__device__ __forceinline__ void group_overlaps(const uint32_t (&w)[kRows],
-                                               const uint32_t (&msk)[kRows], uint32_t ncols,
+template <int RPC, int CPW, int ROWS>
+__device__ __forceinline__ void group_overlaps(const uint32_t (&w)[ROWS],
+                                               const uint32_t (&msk)[ROWS], uint32_t ncols,
                                                uint32_t m, uint32_t (&ovs)[CPW]) {
 #pragma unroll
   for (uint32_t j = 0; j < (uint32_t)CPW; ++j) {
@@ -294,14 +301,14 @@ __device__ __forceinline__ void write_frame(const PersistArgs& a, const uint64_t
 // picks each column's frame-(t+1) overlap accordingly and resolves frame
 // t + 1 as well, so one exchange round trip serves two frames; the results
 // are exactly those of stepping the frames one by one.
-template <int RPC, int NV>
+template <int RPC, int NV, int ROWS>
 __global__ __launch_bounds__(128) void k_sp_persistent(PersistArgs a) {
-  constexpr uint32_t CPW = kRows / RPC;
+  constexpr uint32_t CPW = ROWS / RPC;
   constexpr uint32_t CPAD = NV * 4 * kWave;  // entries per exchange array
   constexpr uint32_t NARR = 3;               // frame t, frame t+1 if lost, if won
   extern __shared__ uint32_t lds[];
-  uint32_t* ring = lds;                         // [kRing][kRows][64] input words
-  uint32_t* ctl = lds + kRing * kRows * kWave;  // [0] produced, [1] consumed, [2] abort
+  uint32_t* ring = lds;                         // [kRing][ROWS][64] input words
+  uint32_t* ctl = lds + kRing * ROWS * kWave;  // [0] produced, [1] consumed, [2] abort
   const Shape sh = a.sh;
   const uint32_t lane = threadIdx.x % kWave;
   const uint32_t c_begin = blockIdx.x * CPW;
@@ -316,9 +323,9 @@ __global__ __launch_bounds__(128) void k_sp_persistent(PersistArgs a) {
 
   if (threadIdx.x >= kWave) {
     // ---- producer wave ----
-    uint32_t wi[kRows];
+    uint32_t wi[ROWS];
 #pragma unroll
-    for (uint32_t r = 0; r < kRows; ++r) {
+    for (uint32_t r = 0; r < ROWS; ++r) {
       const uint32_t j = r / RPC, s = (r % RPC) * kWave + lane;
       const bool ok = j < ncols && s < sh.S;
       const size_t off = ok ? (size_t)(c_begin + j) * sh.S + s : 0;
@@ -334,21 +341,21 @@ __global__ __launch_bounds__(128) void k_sp_persistent(PersistArgs a) {
         __builtin_amdgcn_s_sleep(2);
       }
       const uint32_t* fr = a.frames + (size_t)t * sh.W;
-      uint32_t w[kRows];
+      uint32_t w[ROWS];
 #pragma unroll
-      for (uint32_t r = 0; r < kRows; ++r) w[r] = fr[wi[r]];
-      uint32_t* dst = ring + (t % kRing) * kRows * kWave + lane;
+      for (uint32_t r = 0; r < ROWS; ++r) w[r] = fr[wi[r]];
+      uint32_t* dst = ring + (t % kRing) * ROWS * kWave + lane;
 #pragma unroll
-      for (uint32_t r = 0; r < kRows; ++r) dst[r * kWave] = w[r];
+      for (uint32_t r = 0; r < ROWS; ++r) dst[r * kWave] = w[r];
       lds_release(&ctl[0], t + 1);
     }
     return;
   }
 
   // ---- main wave ----
-  uint32_t st[kRows], msk[kRows];
+  uint32_t st[ROWS], msk[ROWS];
 #pragma unroll
-  for (uint32_t r = 0; r < kRows; ++r) {
+  for (uint32_t r = 0; r < ROWS; ++r) {
     const uint32_t j = r / RPC, s = (r % RPC) * kWave + lane;
     const bool ok = j < ncols && s < sh.S;
     const size_t off = ok ? (size_t)(c_begin + j) * sh.S + s : 0;
@@ -360,7 +367,7 @@ __global__ __launch_bounds__(128) void k_sp_persistent(PersistArgs a) {
   // Rows that hold a synapse in this lane.
   uint32_t row_ok = 0;
 #pragma unroll
-  for (uint32_t r = 0; r < kRows; ++r)
+  for (uint32_t r = 0; r < ROWS; ++r)
     row_ok |= ((r / RPC) < ncols && (r % RPC) * kWave + lane < sh.S) ? 1u << r : 0u;
 
   uint16_t* x16 = reinterpret_cast<uint16_t*>(a.xchg);
@@ -426,12 +433,12 @@ __global__ __launch_bounds__(128) void k_sp_persistent(PersistArgs a) {
       }
     }
     if (abort) break;
-    uint32_t w0[kRows], w1[kRows];
+    uint32_t w0[ROWS], w1[ROWS];
     {
-      const uint32_t* s0 = ring + (t % kRing) * kRows * kWave + lane;
-      const uint32_t* s1 = ring + ((t + 1) % kRing) * kRows * kWave + lane;
+      const uint32_t* s0 = ring + (t % kRing) * ROWS * kWave + lane;
+      const uint32_t* s1 = ring + ((t + 1) % kRing) * ROWS * kWave + lane;
 #pragma unroll
-      for (uint32_t r = 0; r < kRows; ++r) {
+      for (uint32_t r = 0; r < ROWS; ++r) {
         w0[r] = s0[r * kWave];
         w1[r] = two ? s1[r * kWave] : 0u;
       }
@@ -441,18 +448,18 @@ __global__ __launch_bounds__(128) void k_sp_persistent(PersistArgs a) {
     // Frame t's overlaps; frame t + 1's if each column loses frame t (same
     // state) and if it wins it (state after learning frame t).
     uint32_t ov0[CPW], ovL[CPW], ovW[CPW];
-    uint32_t stW[kRows], mskW[kRows];
-    group_overlaps<RPC, CPW>(w0, msk, ncols, sh.m, ov0);
+    uint32_t stW[ROWS], mskW[ROWS];
+    group_overlaps<RPC, CPW, ROWS>(w0, msk, ncols, sh.m, ov0);
 #pragma unroll
-    for (uint32_t r = 0; r < kRows; ++r) {
+    for (uint32_t r = 0; r < ROWS; ++r) {
       const uint32_t i = st[r] >> 9;
       const uint32_t q = learn_q(st[r] & 511u, input_bit(w0[r], i), sh);
       const bool ok = a.learn && ((row_ok >> r) & 1u);  // no learning: both cases agree
       stW[r] = ok ? (i << 9) | q : st[r];
       mskW[r] = ok ? (q >= sh.theta ? 1u << (i & 31u) : 0u) : msk[r];
     }
-    group_overlaps<RPC, CPW>(w1, msk, ncols, sh.m, ovL);
-    group_overlaps<RPC, CPW>(w1, mskW, ncols, sh.m, ovW);
+    group_overlaps<RPC, CPW, ROWS>(w1, msk, ncols, sh.m, ovL);
+    group_overlaps<RPC, CPW, ROWS>(w1, mskW, ncols, sh.m, ovW);
 
     // Publish into every replica.
     const uint32_t g = a.frame_base + t / 2;
@@ -541,7 +548,7 @@ __global__ __launch_bounds__(128) void k_sp_persistent(PersistArgs a) {
       const uint64_t sel0 = __ballot(r0.sel);
       const uint64_t sel1 = two ? __ballot(r1.sel) : 0ull;
 #pragma unroll
-      for (uint32_t r = 0; r < kRows; ++r) {
+      for (uint32_t r = 0; r < ROWS; ++r) {
         const uint32_t j = r / RPC;
         const bool won0 = (sel0 >> j) & 1ull;
         st[r] = won0 ? stW[r] : st[r];
@@ -570,7 +577,7 @@ __global__ __launch_bounds__(128) void k_sp_persistent(PersistArgs a) {
   }
   if (a.learn) {
 #pragma unroll
-    for (uint32_t r = 0; r < kRows; ++r) {
+    for (uint32_t r = 0; r < ROWS; ++r) {
       const uint32_t j = r / RPC, s = (r % RPC) * kWave + lane;
       if ((row_ok >> r) & 1u) a.perm[(size_t)(c_begin + j) * sh.S + s] = q_to_perm(st[r] & 511u);
     }
@@ -579,9 +586,9 @@ __global__ __launch_bounds__(128) void k_sp_persistent(PersistArgs a) {
 
 }  // namespace
 
-size_t persistent_lds_bytes() { return sizeof(uint32_t) * ((size_t)kRing * kRows * kWave + 4); }
-
-uint32_t persistent_rows() { return kRows; }
+size_t persistent_lds_bytes(uint32_t rows) {
+  return sizeof(uint32_t) * ((size_t)kRing * rows * kWave + 4);
+}
 
 uint32_t persistent_exchange_arrays() { return 3; }
 
@@ -591,11 +598,15 @@ uint32_t persistent_exchange_entries(uint32_t C) {
   return nv * 4 * kWave;
 }
 
-const void* persistent_kernel(uint32_t rpc, uint32_t nv) {
-#define HTMSP_PK(P, V) \
-  if (rpc == P && nv == V) return reinterpret_cast<const void*>(&k_sp_persistent<P, V>);
-#define HTMSP_PK_V(P) HTMSP_PK(P, 1) HTMSP_PK(P, 2) HTMSP_PK(P, 4) HTMSP_PK(P, 8) HTMSP_PK(P, 16)
-  HTMSP_PK_V(1) HTMSP_PK_V(2) HTMSP_PK_V(4) HTMSP_PK_V(8) HTMSP_PK_V(16)
+const void* persistent_kernel(uint32_t rpc, uint32_t nv, uint32_t rows) {
+#define HTMSP_PK(P, V, R)                              \
+  if (rpc == P && nv == V && rows == R)                \
+    return reinterpret_cast<const void*>(&k_sp_persistent<P, V, R>);
+#define HTMSP_PK_V(P, R) \
+  HTMSP_PK(P, 1, R) HTMSP_PK(P, 2, R) HTMSP_PK(P, 4, R) HTMSP_PK(P, 8, R) HTMSP_PK(P, 16, R)
+  HTMSP_PK_V(1, 4) HTMSP_PK_V(2, 4) HTMSP_PK_V(4, 4)
+  HTMSP_PK_V(8, 8)
+  HTMSP_PK_V(1, 16) HTMSP_PK_V(2, 16) HTMSP_PK_V(4, 16) HTMSP_PK_V(8, 16) HTMSP_PK_V(16, 16)
 #undef HTMSP_PK_V
 #undef HTMSP_PK
   return nullptr;
@@ -614,17 +625,19 @@ hipError_t launch_check_state(const uint32_t* idx, const float* perm, size_t n, 
 }
 
 hipError_t launch_overlap_plain(const uint32_t* idx, const float* perm, const uint32_t* frame,
-                                int32_t* ov, const Shape& sh, hipStream_t s) {
+                                int32_t* ov, const Shape& sh, hipStream_t s,
+                                const uint32_t* boost) {
   const uint32_t waves_per_block = 4;
   const uint32_t blocks = (sh.C + waves_per_block - 1) / waves_per_block;
   hipLaunchKernelGGL(k_overlap_plain, dim3(blocks), dim3(waves_per_block * kWave), 0, s, idx,
-                     perm, frame, ov, sh);
+                     perm, frame, ov, sh, boost);
   return hipGetLastError();
 }
 
 hipError_t launch_topk_plain(const int32_t* ov, int32_t* winners, const Shape& sh,
-                             hipStream_t s, uint32_t frames) {
-  hipLaunchKernelGGL(k_topk_plain, dim3(frames), dim3(kTopkThreads), 0, s, ov, winners, sh);
+                             hipStream_t s, uint32_t frames, uint32_t vmax) {
+  hipLaunchKernelGGL(k_topk_plain, dim3(frames), dim3(kTopkThreads), 0, s, ov, winners, sh,
+                     vmax ? vmax : sh.S);
   return hipGetLastError();
 }
 

@@ -64,12 +64,11 @@ __device__ bool wait_decision(const ManyInst& in, uint32_t tag, const ManyArgs& 
   }
 }
 
-// floor(p / S) for p < 2^24 from a float reciprocal, corrected to exact.
-__device__ __forceinline__ uint32_t div_s(uint32_t p, uint32_t S, float invS) {
-  uint32_t q = (uint32_t)((float)p * invS);
-  if (q * S > p) --q;
-  else if ((q + 1) * S <= p) ++q;
-  return q;
+// floor(p / S) for p, S < 2^13 as one high multiply by m = ceil(2^32 / S)
+// (exact there: the rounding error of m, times p, stays below 2^-6); S = 1,
+// where m would not fit, is m = 0.
+__device__ __forceinline__ uint32_t div_s(uint32_t p, uint32_t m) {
+  return m ? __umulhi(p, m) : p;
 }
 
 struct TileLds {
@@ -79,7 +78,10 @@ struct TileLds {
 };
 
 // Tile task `slot` of this workgroup, whole workgroup.  Returns false
-// (uniformly) on abort.
+// (uniformly) on abort.  ALIGNED (S a multiple of 64): every 64-synapse
+// chunk of a wave lies in one column, so the column, its "won" flag and its
+// count are wave-uniform.
+template <bool ALIGNED>
 __device__ bool tile_step(const ManyArgs& a, const ManyInst& in, uint32_t c0, uint32_t c1,
                           uint32_t t, uint32_t slot, TileLds& L) {
   const Shape& sh = in.sh;
@@ -89,13 +91,13 @@ __device__ bool tile_step(const ManyArgs& a, const ManyInst& in, uint32_t c0, ui
   const uint32_t ncol = c1 - c0, nsyn = ncol * sh.S;
   const bool learn_now = a.learn && t > 0;
   const bool overlap_now = t < in.F;
+  const uint32_t m = in.smagic;
 
   // The state does not depend on the decision: its loads are in flight
   // while thread 0 waits.
   const size_t p0 = (size_t)c0 * sh.S;
   const uint32_t* gidx = in.idx + p0;
   float* gperm = in.perm + p0;
-  const float invS = 1.0f / (float)sh.S;
   uint32_t ix[kPerThread], q[kPerThread];
 #pragma unroll
   for (uint32_t j = 0; j < kPerThread; ++j) {
@@ -114,11 +116,15 @@ __device__ bool tile_step(const ManyArgs& a, const ManyInst& in, uint32_t c0, ui
   __syncthreads();
   if (!L.bc[0]) return false;
   const uint32_t T = L.bc[1], clast1 = L.bc[2];
+  // column cl of this tile won frame t - 1 (its overlap of that frame is the
+  // one this tile published last step)
+  auto won_col = [&](uint32_t cl) {
+    const uint32_t prev = L.prev[slot][cl];
+    return prev > T || (T != 0 && prev == T && c0 + cl + 1 <= clast1);
+  };
 
-  // Which synapses belong to a column that won frame t - 1 (its overlap of
-  // that frame is the one this tile published last step), then both input
-  // gathers in one round: frame t - 1 for learning, frame t for every
-  // synapse that can be connected after learning.
+  // Both input gathers in one round: frame t - 1 for learning, frame t for
+  // every synapse that can be connected after learning.
   const uint32_t* fprev = in.frames + (size_t)(learn_now ? t - 1 : 0) * sh.W;
   const uint32_t* fcur = in.frames + (size_t)(overlap_now ? t : 0) * sh.W;
   uint32_t won = 0;  // bit j: synapse j belongs to a winner
@@ -127,10 +133,11 @@ __device__ bool tile_step(const ManyArgs& a, const ManyInst& in, uint32_t c0, ui
   for (uint32_t j = 0; j < kPerThread; ++j) {
     const uint32_t p = tid + kManyThreads * j;
     bool wj = false;
-    if (learn_now && p < nsyn) {
-      const uint32_t cl = div_s(p, sh.S, invS);
-      const uint32_t prev = L.prev[slot][cl];
-      wj = prev > T || (T != 0 && prev == T && c0 + cl + 1 <= clast1);
+    if constexpr (ALIGNED) {
+      const uint32_t pb = kManyThreads * j + kWave * wave;  // uniform
+      wj = learn_now && pb < nsyn && won_col(div_s(pb, m));
+    } else {
+      wj = learn_now && p < nsyn && won_col(div_s(p, m));
     }
     won |= (uint32_t)wj << j;
     wp[j] = wj ? fprev[ix[j] >> 5] : 0u;
@@ -153,16 +160,21 @@ __device__ bool tile_step(const ManyArgs& a, const ManyInst& in, uint32_t c0, ui
       const bool hit = (pb + lane < nsyn) && q[j] >= sh.theta && input_bit(wc[j], ix[j]);
       const uint64_t mask = __ballot(hit);
       if (pb < nsyn && mask) {
-        // columns that meet the chunk [pb, pb + 64): lane l counts column clA + l
-        const uint32_t clA = div_s(pb, sh.S, invS);
-        const uint32_t clB = div_s(min(pb + kWave, nsyn) - 1, sh.S, invS);
-        const uint32_t cl = clA + lane;
-        if (cl <= clB) {
-          const uint32_t lo = max(cl * sh.S, pb) - pb;
-          const uint32_t hi = min((cl + 1) * sh.S, pb + kWave) - pb;
-          const uint64_t bits = hi - lo == 64 ? mask : (mask >> lo) & ((1ull << (hi - lo)) - 1);
-          const uint32_t n = (uint32_t)__popcll(bits);
-          if (n) atomicAdd(&L.cnt[cl], n);
+        if constexpr (ALIGNED) {
+          if (lane == 0) atomicAdd(&L.cnt[div_s(pb, m)], (uint32_t)__popcll(mask));
+        } else {
+          // columns that meet the chunk [pb, pb + 64): lane l counts column clA + l
+          const uint32_t clA = div_s(pb, m);
+          const uint32_t clB = div_s(min(pb + kWave, nsyn) - 1, m);
+          const uint32_t cl = clA + lane;
+          if (cl <= clB) {
+            const uint32_t lo = max(cl * sh.S, pb) - pb;
+            const uint32_t hi = min((cl + 1) * sh.S, pb + kWave) - pb;
+            const uint64_t bits =
+                hi - lo == 64 ? mask : (mask >> lo) & ((1ull << (hi - lo)) - 1);
+            const uint32_t n = (uint32_t)__popcll(bits);
+            if (n) atomicAdd(&L.cnt[cl], n);
+          }
         }
       }
     }
@@ -183,80 +195,80 @@ __device__ bool tile_step(const ManyArgs& a, const ManyInst& in, uint32_t c0, ui
 // Top-k task, one wave: collects the instance's overlaps of step t, resolves
 // the global top-k, writes the outputs and publishes the decision.  Lane l
 // holds columns u * 256 + 4l + q (q < 4) as the 16-bit fields of ev[u].
+// Registers are kept to ev[] plus per-word temporaries: the entries are
+// folded into ev[] as they arrive (a stale mask marks pairs to load again),
+// and the winners are selected word by word while they are written.
 __device__ bool topk_step(const ManyArgs& a, ManyInst& in, uint32_t t, uint32_t lane) {
   const Shape& sh = in.sh;
   const uint32_t tag = (in.step_base + t + 1) & 0xFFFFu;
   const uint32_t nv = (sh.C + 4 * kWave - 1) / (4 * kWave);
   const uint64_t* src = reinterpret_cast<const uint64_t*>(in.ovx);
-  // two 64-bit loads (columns c, c + 1 and c + 2, c + 3) per word, all in
-  // flight at once; stale pairs are loaded again until every tag matches
-  uint64_t raw[2 * kManyNV];
+  uint64_t ev[kManyNV];
+#pragma unroll
+  for (uint32_t u = 0; u < kManyNV; ++u) ev[u] = 0;
+  // pair i holds columns c, c + 1 (c = (i / 2) * 256 + 4l + 2 (i % 2)); all
+  // loads of a pass are in flight at once
+  uint32_t stale = 0;
 #pragma unroll
   for (uint32_t i = 0; i < 2 * kManyNV; ++i) {
     const uint32_t c = (i / 2) * 4 * kWave + 4 * lane + 2 * (i % 2);
-    raw[i] = (i / 2 < nv && c < sh.C) ? load_word(src + c / 2) : 0ull;
+    if (i / 2 < nv && c < sh.C) stale |= 1u << i;
   }
   uint32_t spins = 0;
-  bool bad = false;
   while (true) {
-    uint32_t stale = 0;
+    uint32_t still = 0;
 #pragma unroll
     for (uint32_t i = 0; i < 2 * kManyNV; ++i) {
-      const uint32_t c = (i / 2) * 4 * kWave + 4 * lane + 2 * (i % 2);
-      if (i / 2 < nv && c < sh.C) {
-        const bool ok0 = (uint32_t)(raw[i] >> 16) % 65536u == tag;
-        const bool ok1 = c + 1 >= sh.C || (uint32_t)(raw[i] >> 48) == tag;
-        stale |= (uint32_t)!(ok0 && ok1) << i;
-      }
-    }
-    if (!__any(stale != 0)) break;
-    if (++spins > a.spin_limit || ((spins & 63u) == 0 && load_tagged(a.err) != 0)) {
-      bad = true;
-      break;
-    }
-    __builtin_amdgcn_s_sleep(1);
-#pragma unroll
-    for (uint32_t i = 0; i < 2 * kManyNV; ++i)
       if (stale & (1u << i)) {
         const uint32_t c = (i / 2) * 4 * kWave + 4 * lane + 2 * (i % 2);
-        raw[i] = load_word(src + c / 2);
+        const uint64_t r = load_word(src + c / 2);
+        const bool ok0 = (uint32_t)(r >> 16) % 65536u == tag;
+        const bool ok1 = c + 1 >= sh.C || (uint32_t)(r >> 48) == tag;
+        if (ok0 && ok1) {
+          const uint64_t v = (r & 0xFFFFull) | (c + 1 < sh.C ? ((r >> 32) & 0xFFFFull) << 16 : 0ull);
+          ev[i / 2] |= v << (32 * (i % 2));
+        } else {
+          still |= 1u << i;
+        }
       }
-  }
-  if (bad) return false;
-  uint64_t ev[kManyNV];
-#pragma unroll
-  for (uint32_t u = 0; u < kManyNV; ++u) {
-    uint64_t v = 0;
-    if (u < nv) {
-      const uint32_t c = u * 4 * kWave + 4 * lane;
-      const uint64_t r0 = raw[2 * u], r1 = raw[2 * u + 1];
-      v = (r0 & 0xFFFFull) | (c + 1 < sh.C ? ((r0 >> 32) & 0xFFFFull) << 16 : 0ull) |
-          (c + 2 < sh.C ? (r1 & 0xFFFFull) << 32 : 0ull) |
-          (c + 3 < sh.C ? ((r1 >> 32) & 0xFFFFull) << 48 : 0ull);
-      if (c >= sh.C) v = 0;
     }
-    ev[u] = v;
+    stale = still;
+    if (!__any(stale != 0)) break;
+    if (++spins > a.spin_limit || ((spins & 63u) == 0 && load_tagged(a.err) != 0)) return false;
+    __builtin_amdgcn_s_sleep(1);
   }
   uint32_t c_hi;
   const uint32_t T = topk_threshold(ev, sh.S, sh.k, in.guess, &c_hi);
   const uint32_t need = T ? sh.k - c_hi : 0u;
   const uint32_t nsel = T ? sh.k : c_hi;
   if (T) in.guess = T;
-  uint64_t fm[kManyNV];
-  select_all(ev, T, need, lane, fm);
 
+  // Winners word by word: every field above T, and the first `need` fields
+  // equal to T in column order; ranks by prefix counts over the lanes.
   int32_t* wrow = in.win_out + (size_t)t * sh.k;
-  uint32_t base = 0, clast1 = 0;
-  const uint64_t k_ge = (uint64_t)(0x8000u - (T ? T : 1u)) * kOnes16;
   const uint64_t k_gt = (uint64_t)(0x8000u - (T + 1)) * kOnes16;
+  const uint64_t k_ge = (uint64_t)(0x8000u - T) * kOnes16;
+  uint32_t eq_before = 0, sel_before = 0, clast1 = 0;
 #pragma unroll
   for (uint32_t u = 0; u < kManyNV; ++u) {
     if (u < nv) {
-      const uint64_t sel = fm[u] & kHighBits;
-      const uint64_t eq =
-          T ? (((ev[u] + k_ge) & kHighBits) & ~((ev[u] + k_gt) & kHighBits)) & sel : 0ull;
+      const uint64_t gt = (ev[u] + k_gt) & kHighBits;
+      const uint64_t eq = T ? (((ev[u] + k_ge) & kHighBits) & ~gt) : 0ull;
+      const uint32_t neq = (uint32_t)__popcll(eq);
+      const uint32_t pre = eq_before + wave_prefix<3>(neq, lane);
+      uint32_t keep = need > pre ? need - pre : 0u;
+      uint64_t take = 0;
+#pragma unroll
+      for (uint32_t q = 0; q < 4; ++q) {
+        const uint64_t bit = eq & (0x8000ull << (16 * q));
+        const bool use = bit != 0ull && keep > 0;
+        take |= use ? bit : 0ull;
+        keep -= use ? 1u : 0u;
+      }
+      eq_before += wave_count<3>(neq);
+      const uint64_t sel = gt | take;
       const uint32_t n = (uint32_t)__popcll(sel);
-      uint32_t pos = base + wave_prefix<3>(n, lane);
+      uint32_t pos = sel_before + wave_prefix<3>(n, lane);
 #pragma unroll
       for (uint32_t q = 0; q < 4; ++q) {
         const uint32_t c = u * 4 * kWave + 4 * lane + q;
@@ -266,11 +278,11 @@ __device__ bool topk_step(const ManyArgs& a, ManyInst& in, uint32_t t, uint32_t 
           // this wave is the instance's only histogram writer in the launch
           if (in.hist) in.hist[c] += 1u;
         }
-        if (eq & (0x8000ull << (16 * q))) clast1 = max(clast1, c + 1);
+        if (take & (0x8000ull << (16 * q))) clast1 = max(clast1, c + 1);
         if (in.ov_out && c < sh.C)
           in.ov_out[(size_t)t * sh.C + c] = (int32_t)((ev[u] >> (16 * q)) & 0xFFFFu);
       }
-      base += wave_count<3>(n);
+      sel_before += wave_count<3>(n);
     }
   }
   for (uint32_t i = nsel + lane; i < sh.k; i += kWave) wrow[i] = -1;
@@ -283,6 +295,9 @@ __device__ bool topk_step(const ManyArgs& a, ManyInst& in, uint32_t t, uint32_t 
 
 // Two waves per SIMD (at most 256 registers): two tiles in flight per CU
 // already keep more bytes in flight than device memory needs to stream.
+// ALIGNED: every instance of the launch has S a multiple of 64 (one tile
+// path per kernel keeps the register allocation free of spills).
+template <bool ALIGNED>
 __global__ __launch_bounds__(kManyThreads, 2) void k_sp_many(ManyArgs a) {
   __shared__ TileLds L;
   // per-step abort flags, alternating so that a flag is never written while
@@ -301,7 +316,7 @@ __global__ __launch_bounds__(kManyThreads, 2) void k_sp_many(ManyArgs a) {
       if (t > in.F) continue;
       if (task.kind == 0) {
         // the host deals at most kMaxTileSlots tiles, first, to a workgroup
-        ok = j - t0 < kMaxTileSlots && tile_step(a, in, task.c0, task.c1, t, j - t0, L);
+        ok = j - t0 < kMaxTileSlots && tile_step<ALIGNED>(a, in, task.c0, task.c1, t, j - t0, L);
       } else if (t < in.F && wave == 0) {
         ok = topk_step(a, in, t, lane);
       }
@@ -320,19 +335,24 @@ uint32_t many_tile_columns(uint32_t S) {
   return std::min(kTileColumns, std::max(1u, kTileSynapses / S));
 }
 
-hipError_t launch_many(const ManyArgs& a, uint32_t grid, hipStream_t s) {
-  ManyArgs copy = a;
-  void* args[] = {&copy};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_sp_many), dim3(grid),
-                                    dim3(kManyThreads), args, 0, s);
+static const void* many_kernel(bool aligned) {
+  return aligned ? reinterpret_cast<const void*>(&k_sp_many<true>)
+                 : reinterpret_cast<const void*>(&k_sp_many<false>);
 }
 
-int many_max_blocks(int device) {
+hipError_t launch_many(const ManyArgs& a, uint32_t grid, bool aligned, hipStream_t s) {
+  ManyArgs copy = a;
+  void* args[] = {&copy};
+  return hipLaunchCooperativeKernel(many_kernel(aligned), dim3(grid), dim3(kManyThreads), args,
+                                    0, s);
+}
+
+int many_max_blocks(int device, bool aligned) {
   int cus = 0, per_cu = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
     return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &per_cu, reinterpret_cast<const void*>(&k_sp_many), kManyThreads, 0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, many_kernel(aligned), kManyThreads,
+                                                   0) != hipSuccess)
     return 0;
   return cus * per_cu;
 }

@@ -113,6 +113,33 @@ def blob_frames(g: np.random.Generator, frames: int, width: int, height: int,
     return out
 
 
+def rgb_frames(g: np.random.Generator, frames: int, width: int, height: int,
+               shapes: int = 12) -> np.ndarray:
+    """uint8 [F][H][W][3] colour frames standing in for rendered video:
+    a smooth illumination gradient whose direction varies per frame, solid
+    rectangles and discs of random colour, and uniform noise of +-8 levels."""
+    yy, xx = np.mgrid[0:height, 0:width].astype(np.float32)
+    out = np.empty((frames, height, width, 3), dtype=np.uint8)
+    for t in range(frames):
+        ang = g.uniform(0, 2 * np.pi)
+        base = g.uniform(40, 120, size=3).astype(np.float32)
+        ramp = (np.cos(ang) * xx / max(width, 1) + np.sin(ang) * yy / max(height, 1)) * 90.0
+        img = base[None, None, :] + ramp[:, :, None]
+        for _ in range(shapes):
+            col = g.uniform(0, 255, size=3).astype(np.float32)
+            cx, cy = g.uniform(0, width), g.uniform(0, height)
+            rx = g.uniform(0.02, 0.15) * width
+            ry = g.uniform(0.02, 0.15) * height
+            if g.random() < 0.5:
+                m = (np.abs(xx - cx) < rx) & (np.abs(yy - cy) < ry)
+            else:
+                m = ((xx - cx) / rx) ** 2 + ((yy - cy) / ry) ** 2 < 1.0
+            img[m] = col
+        img += g.uniform(-8, 8, size=img.shape).astype(np.float32)
+        out[t] = np.clip(img + 0.5, 0, 255).astype(np.uint8)
+    return out
+
+
 @dataclass
 class Workload:
     """One spatial pooler instance plus its input frames."""

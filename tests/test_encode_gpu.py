@@ -1,0 +1,85 @@
+"""The GPU adaptive video encoder (Section 3.1.2) against the encoder
+oracle, bit for bit: ragged and tiny frames, every window size, reduction
+factors, the 960x540 frame, the encoded frames fed to the pooler, and
+rejected configurations."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1608_01966_amd as sp
+from paper_1608_01966_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _check(rgb, factor, block, offset):
+    import torch
+    got = sp.sp_encode(torch.from_numpy(rgb).cuda(), factor, block, offset)
+    torch.cuda.synchronize()
+    want = oracle.enc_frames(rgb, factor, block, offset)
+    got = got.cpu().numpy().view(np.uint32)
+    bad = np.argwhere(got != want)
+    assert bad.size == 0, f"{rgb.shape} f={factor} b={block} c={offset}: words {bad[:5].tolist()}"
+
+
+@pytest.mark.parametrize("W,H,factor,block,offset", [
+    (1, 1, 1, 3, 2), (7, 5, 1, 3, 0), (33, 17, 1, 5, 2), (63, 64, 1, 11, -3),
+    (64, 2, 1, 7, 5), (65, 40, 1, 9, 2), (130, 77, 2, 11, 2), (241, 135, 3, 5, 1),
+    (500, 301, 1, 11, 2), (960, 540, 4, 11, 2), (1921, 37, 1, 3, 2), (4096, 20, 1, 11, 2),
+    (8192, 9, 2, 5, 2),
+])
+def test_shapes(W, H, factor, block, offset):
+    rgb = synth.rgb_frames(synth.rng(W * 7 + H, 6), 3, W, H)
+    _check(rgb, factor, block, offset)
+
+
+@pytest.mark.parametrize("block", [3, 5, 7, 9, 11])
+def test_every_window_on_noise(block):
+    g = np.random.default_rng(block)
+    rgb = g.integers(0, 256, size=(2, 45, 100, 3), dtype=np.uint8)
+    _check(rgb, 1, block, 2)
+
+
+def test_paper_frame_size():
+    rgb = synth.rgb_frames(synth.rng(11, 6), 4, 960, 540)
+    _check(rgb, 1, 11, 2)
+
+
+def test_flat_frames():
+    rgb = np.full((2, 30, 70, 3), 128, dtype=np.uint8)
+    _check(rgb, 1, 11, 2)
+    _check(rgb, 1, 11, 0)
+
+
+def test_encoded_frames_drive_the_pooler():
+    """Encoder then pooler on the GPU equals encoder then pooler in the
+    oracle (the raw-frame front end of the path)."""
+    import torch
+    rgb = synth.rgb_frames(synth.rng(12, 6), 20, 480, 270)
+    n = sp.sp_encoded_bits(480, 270, 2)
+    assert n == 240 * 135
+    cfg = synth.sp_config(n, 512, 128, 4, 20)
+    w = synth.random_instance(13, cfg, 0)
+    pool = sp.SpatialPooler(cfg, w.idx, w.perm)
+    frames = sp.sp_encode(torch.from_numpy(rgb).cuda(), factor=2)
+    ov, win = pool.step(frames)
+    pool.sync()
+    e_frames = oracle.enc_frames(rgb, 2)
+    e_ov, e_win, e_perm = oracle.run(cfg, w.idx, w.perm, e_frames)
+    assert np.array_equal(ov.cpu().numpy(), e_ov)
+    assert np.array_equal(win.cpu().numpy(), e_win)
+    assert np.array_equal(pool.perm.cpu().numpy().astype(np.float64), e_perm)
+    pool.close()
+
+
+def test_rejects_bad_configurations():
+    import torch
+    rgb = torch.zeros((1, 8, 8, 3), dtype=torch.uint8, device="cuda")
+    for kw in ({"block": 4}, {"block": 13}, {"block": 1}, {"factor": 0}, {"factor": 9},
+               {"offset": 300}):
+        with pytest.raises(sp.SpError):
+            sp.sp_encode(rgb, **kw)
+    wide = torch.zeros((1, 2, 4097, 3), dtype=torch.uint8, device="cuda")
+    with pytest.raises(sp.SpError):
+        sp.sp_encode(wide)
+    assert sp.sp_encoded_bits(4097, 2) == 0

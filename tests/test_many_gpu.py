@@ -94,6 +94,20 @@ def test_without_overlaps():
     check(mixed(7, 3, 8), want_ov=False)
 
 
+def test_aligned_synapse_counts_ragged_columns():
+    """Only S that are multiples of 64 (the aligned kernel), including S that
+    are not powers of two, with ragged column counts and input sizes."""
+    g = np.random.default_rng(12)
+    ws = []
+    for i, S in enumerate([64, 192, 320, 128, 448, 64]):
+        N = int(g.integers(S, 90000))
+        C = int(g.integers(1, 2500))
+        cfg = synth.sp_config(N, C, S, int(g.integers(0, 6)), int(g.integers(1, C + 1)))
+        ws.append(synth.random_instance(1200 + i, cfg, frames=10,
+                                        density=float(g.uniform(0.02, 0.3))))
+    check(ws)
+
+
 def test_largest_instances():
     """4096 columns x 512 synapses and the 960x540 input in one batch with
     small instances."""

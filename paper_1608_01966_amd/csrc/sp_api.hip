@@ -199,26 +199,20 @@ void plan_persistent(sp_handle* h) {
     return;
   const uint32_t rpc = next_pow2((sh.S + 63) / 64);
   const uint32_t nv = next_pow2(htmsp::persistent_exchange_entries(sh.C) / 256);
-  // The fewest rows per workgroup (most workgroups) whose grid is
-  // co-resident, else 16.
-  const uint32_t small = std::max(rpc, htmsp::kPersistMinRows);
-  for (uint32_t rows : {small, 16u}) {
-    if (rows < small) continue;
-    const void* k = htmsp::persistent_kernel(rpc, nv, rows);
-    if (!k) continue;
-    const uint32_t cpw = rows / rpc;
-    const uint32_t grid = (sh.C + cpw - 1) / cpw;
-    const size_t lds = htmsp::persistent_lds_bytes(rows);
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 128, lds) != hipSuccess) return;
-    if ((uint64_t)per_cu * (uint64_t)cus < grid) continue;
-    h->grid = grid;
-    h->replicas = htmsp::kPersistReplicas;
-    h->pkernel = k;
-    h->plds = lds;
-    h->persistent = true;
-    return;
-  }
+  const uint32_t rows = htmsp::kPersistRows;
+  const void* k = htmsp::persistent_kernel(rpc, nv, rows);
+  if (!k) return;
+  const uint32_t cpw = rows / rpc;
+  const uint32_t grid = (sh.C + cpw - 1) / cpw;
+  const size_t lds = htmsp::persistent_lds_bytes(rows);
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 128, lds) != hipSuccess) return;
+  if ((uint64_t)per_cu * (uint64_t)cus < grid) return;
+  h->grid = grid;
+  h->replicas = htmsp::kPersistReplicas;
+  h->pkernel = k;
+  h->plds = lds;
+  h->persistent = true;
 }
 
 int run_check_state(sp_handle* h, hipStream_t s) {

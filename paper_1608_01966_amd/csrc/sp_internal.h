@@ -41,9 +41,11 @@ constexpr uint32_t kPersistReplicas = 2;
 
 // LDS of one persistent workgroup holding `rows` rows of 64 synapses.
 size_t persistent_lds_bytes(uint32_t rows);
-// Smallest rows per workgroup the persistent kernel is built for (it also
-// exists for 8 rows when rpc = 8 and for 16 rows).
-constexpr uint32_t kPersistMinRows = 4;
+// Rows of 64 synapses per persistent workgroup.  Fewer rows (more
+// workgroups) shorten each workgroup's serial chain but multiply the
+// readers of the per-frame exchange; measured at 960x540, 1024 x 256:
+// 4 rows (1024 workgroups) ran 2.7x slower than 16 rows (256 workgroups).
+constexpr uint32_t kPersistRows = 16;
 // Exchange arrays per slot (frame t, frame t+1 if lost, frame t+1 if won).
 uint32_t persistent_exchange_arrays();
 // 16-bit exchange entries per array for C columns: 256 times the power of two
@@ -51,7 +53,7 @@ uint32_t persistent_exchange_arrays();
 uint32_t persistent_exchange_entries(uint32_t C);
 // The kernel instance for `rpc` rows per column (1, 2, 4, 8 or 16), `nv`
 // 64-bit exchange words per lane (1, 2, 4, 8 or 16) and `rows` rows per
-// workgroup (max(rpc, 4) or 16); nullptr otherwise.
+// workgroup (kPersistRows); nullptr otherwise.
 const void* persistent_kernel(uint32_t rpc, uint32_t nv, uint32_t rows);
 
 hipError_t launch_check_state(const uint32_t* idx, const float* perm, size_t n, uint32_t N,
@@ -123,7 +125,7 @@ hipError_t launch_hist_add(const int32_t* winners, size_t n, uint32_t C, uint32_
 
 // Many instances in one persistent launch (sp_many.hip).
 constexpr uint32_t kManyNV = 16;          // top-k words per lane: C <= 4096
-constexpr uint32_t kTileSynapses = 4096;  // synapses per tile task (at most)
+constexpr uint32_t kTileSynapses = 8192;  // synapses per tile task (at most)
 constexpr uint32_t kTileColumns = 1024;   // columns per tile task (at most)
 constexpr uint32_t kManyThreads = 256;
 constexpr uint32_t kMaxTileSlots = 16;    // tile tasks per workgroup (at most)

@@ -169,9 +169,7 @@ __global__ __launch_bounds__(256) void k_learn_plain(const uint32_t* __restrict_
 //
 // Workgroup g (two waves) owns CPW = ROWS / RPC consecutive columns from
 // g*CPW; row r holds synapses (r % RPC)*64 + lane of local column r / RPC.
-// Fewer rows per workgroup means more workgroups, each with a shorter serial
-// chain of per-frame work; the host picks the smallest ROWS whose grid is
-// co-resident.
+// ROWS is 16 (see kPersistRows).
 //   wave 0 (main) keeps the synapse state in registers for the whole launch
 //     (idx << 9 | q, plus the mask of the input bit when connected) and, per
 //     frame: overlap of its columns, publish, collect every column's
@@ -604,8 +602,6 @@ const void* persistent_kernel(uint32_t rpc, uint32_t nv, uint32_t rows) {
     return reinterpret_cast<const void*>(&k_sp_persistent<P, V, R>);
 #define HTMSP_PK_V(P, R) \
   HTMSP_PK(P, 1, R) HTMSP_PK(P, 2, R) HTMSP_PK(P, 4, R) HTMSP_PK(P, 8, R) HTMSP_PK(P, 16, R)
-  HTMSP_PK_V(1, 4) HTMSP_PK_V(2, 4) HTMSP_PK_V(4, 4)
-  HTMSP_PK_V(8, 8)
   HTMSP_PK_V(1, 16) HTMSP_PK_V(2, 16) HTMSP_PK_V(4, 16) HTMSP_PK_V(8, 16) HTMSP_PK_V(16, 16)
 #undef HTMSP_PK_V
 #undef HTMSP_PK

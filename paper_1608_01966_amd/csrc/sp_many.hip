@@ -41,11 +41,41 @@ using namespace dev;
 
 constexpr uint32_t kPerThread = kTileSynapses / kManyThreads;  // 32
 
-__device__ __forceinline__ uint64_t load_word(const uint64_t* p) {
+// The instance descriptors live in device memory, so the compiler cannot
+// tell that their pointers address global memory and would use flat
+// accesses, which wait on LDS traffic too and do not batch; every access
+// below goes through these global-space views instead.
+#define HTMSP_G __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ HTMSP_G T* gbl(T* p) {
+  return (HTMSP_G T*)p;
+}
+
+// A descriptor copied word by word through a global-space view.
+template <typename T>
+__device__ __forceinline__ T load_desc(const T* p) {
+  static_assert(sizeof(T) % 4 == 0, "descriptor size");
+  T v;
+  const HTMSP_G uint32_t* src = gbl(reinterpret_cast<const uint32_t*>(p));
+  uint32_t* dst = reinterpret_cast<uint32_t*>(&v);
+#pragma unroll
+  for (uint32_t i = 0; i < sizeof(T) / 4; ++i) dst[i] = src[i];
+  return v;
+}
+
+__device__ __forceinline__ uint64_t load_word(const HTMSP_G uint64_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ void store_word64(uint64_t* p, uint64_t v) {
+__device__ __forceinline__ void store_word64(HTMSP_G uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint32_t load_entry(const HTMSP_G uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void store_entry(HTMSP_G uint32_t* p, uint32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -53,13 +83,15 @@ __device__ __forceinline__ void store_word64(uint64_t* p, uint64_t v) {
 __device__ bool wait_decision(const ManyInst& in, uint32_t tag, const ManyArgs& a,
                               uint64_t* out) {
   uint32_t spins = 0;
+  const HTMSP_G uint64_t* dec = gbl(in.dec);
   while (true) {
-    const uint64_t d = load_word(in.dec);
+    const uint64_t d = load_word(dec);
     if ((uint32_t)(d >> 48) == tag) {
       *out = d;
       return true;
     }
-    if (++spins > a.spin_limit || ((spins & 63u) == 0 && load_tagged(a.err) != 0)) return false;
+    if (++spins > a.spin_limit || ((spins & 63u) == 0 && load_entry(gbl(a.err)) != 0))
+      return false;
     __builtin_amdgcn_s_sleep(1);
   }
 }
@@ -96,15 +128,22 @@ __device__ bool tile_step(const ManyArgs& a, const ManyInst& in, uint32_t c0, ui
   // The state does not depend on the decision: its loads are in flight
   // while thread 0 waits.
   const size_t p0 = (size_t)c0 * sh.S;
-  const uint32_t* gidx = in.idx + p0;
-  float* gperm = in.perm + p0;
+  const HTMSP_G uint32_t* gidx = gbl(in.idx + p0);
+  HTMSP_G float* gperm = gbl(in.perm + p0);
+  // loads without branches (past the tile: its last synapse, then ignored),
+  // so that all of them are in flight together
   uint32_t ix[kPerThread], q[kPerThread];
 #pragma unroll
   for (uint32_t j = 0; j < kPerThread; ++j) {
-    const uint32_t p = tid + kManyThreads * j;
-    const bool v = p < nsyn;
-    ix[j] = v ? min(gidx[p], sh.N - 1) : 0u;
-    q[j] = v ? perm_to_q(gperm[p]) : 0u;
+    const uint32_t p = min(tid + kManyThreads * j, nsyn - 1);
+    ix[j] = gidx[p];
+    q[j] = perm_to_q(gperm[p]);
+  }
+#pragma unroll
+  for (uint32_t j = 0; j < kPerThread; ++j) {
+    const bool v = tid + kManyThreads * j < nsyn;
+    ix[j] = v ? min(ix[j], sh.N - 1) : 0u;
+    q[j] = v ? q[j] : 0u;
   }
   if (tid == 0) {
     uint64_t d = 0;
@@ -125,8 +164,8 @@ __device__ bool tile_step(const ManyArgs& a, const ManyInst& in, uint32_t c0, ui
 
   // Both input gathers in one round: frame t - 1 for learning, frame t for
   // every synapse that can be connected after learning.
-  const uint32_t* fprev = in.frames + (size_t)(learn_now ? t - 1 : 0) * sh.W;
-  const uint32_t* fcur = in.frames + (size_t)(overlap_now ? t : 0) * sh.W;
+  const HTMSP_G uint32_t* fprev = gbl(in.frames + (size_t)(learn_now ? t - 1 : 0) * sh.W);
+  const HTMSP_G uint32_t* fcur = gbl(in.frames + (size_t)(overlap_now ? t : 0) * sh.W);
   uint32_t won = 0;  // bit j: synapse j belongs to a winner
   uint32_t wp[kPerThread], wc[kPerThread];
 #pragma unroll
@@ -140,9 +179,10 @@ __device__ bool tile_step(const ManyArgs& a, const ManyInst& in, uint32_t c0, ui
       wj = learn_now && p < nsyn && won_col(div_s(p, m));
     }
     won |= (uint32_t)wj << j;
-    wp[j] = wj ? fprev[ix[j] >> 5] : 0u;
+    // unneeded gathers read word 0 (one cached line) instead of branching
+    wp[j] = fprev[wj ? ix[j] >> 5 : 0u];
     const bool maybe = overlap_now && p < nsyn && (wj ? q[j] + sh.inc : q[j]) >= sh.theta;
-    wc[j] = maybe ? fcur[ix[j] >> 5] : 0u;
+    wc[j] = fcur[maybe ? ix[j] >> 5 : 0u];
   }
   if (won) {
 #pragma unroll
@@ -186,7 +226,7 @@ __device__ bool tile_step(const ManyArgs& a, const ManyInst& in, uint32_t c0, ui
       L.cnt[cl] = 0;
       const uint32_t ov = raw >= sh.m ? raw : 0u;
       L.prev[slot][cl] = (uint16_t)ov;
-      store_tagged(in.ovx + c0 + cl, (tag << 16) | ov);
+      store_entry(gbl(in.ovx) + c0 + cl, (tag << 16) | ov);
     }
   }
   return true;
@@ -195,47 +235,66 @@ __device__ bool tile_step(const ManyArgs& a, const ManyInst& in, uint32_t c0, ui
 // Top-k task, one wave: collects the instance's overlaps of step t, resolves
 // the global top-k, writes the outputs and publishes the decision.  Lane l
 // holds columns u * 256 + 4l + q (q < 4) as the 16-bit fields of ev[u].
-// Registers are kept to ev[] plus per-word temporaries: the entries are
-// folded into ev[] as they arrive (a stale mask marks pairs to load again),
-// and the winners are selected word by word while they are written.
+// Registers are kept to ev[] plus per-word temporaries past the first
+// collection pass, and the winners are selected word by word while they are
+// written.
 __device__ bool topk_step(const ManyArgs& a, ManyInst& in, uint32_t t, uint32_t lane) {
   const Shape& sh = in.sh;
   const uint32_t tag = (in.step_base + t + 1) & 0xFFFFu;
   const uint32_t nv = (sh.C + 4 * kWave - 1) / (4 * kWave);
-  const uint64_t* src = reinterpret_cast<const uint64_t*>(in.ovx);
+  const HTMSP_G uint64_t* src = gbl(reinterpret_cast<const uint64_t*>(in.ovx));
   uint64_t ev[kManyNV];
 #pragma unroll
   for (uint32_t u = 0; u < kManyNV; ++u) ev[u] = 0;
-  // pair i holds columns c, c + 1 (c = (i / 2) * 256 + 4l + 2 (i % 2)); all
-  // loads of a pass are in flight at once
+  // pair i holds columns c, c + 1 (c = (i / 2) * 256 + 4l + 2 (i % 2)).  The
+  // first pass has every load in flight at once; pairs whose tags are not
+  // yet those of step t are read again, one by one, until they are.
+  auto pair_col = [&](uint32_t i) { return (i / 2) * 4 * kWave + 4 * lane + 2 * (i % 2); };
+  auto fresh = [&](uint64_t r, uint32_t c) {
+    return (uint32_t)(r >> 16) % 65536u == tag && (c + 1 >= sh.C || (uint32_t)(r >> 48) == tag);
+  };
+  auto fold = [&](uint64_t r, uint32_t i, uint32_t c) {
+    const uint64_t v = (r & 0xFFFFull) | (c + 1 < sh.C ? ((r >> 32) & 0xFFFFull) << 16 : 0ull);
+    ev[i / 2] |= v << (32 * (i % 2));
+  };
   uint32_t stale = 0;
+  // (in two halves: 16 loads in flight, 1024 + 1024 columns, keep the
+  // register peak of this pass below that of the tile path)
 #pragma unroll
-  for (uint32_t i = 0; i < 2 * kManyNV; ++i) {
-    const uint32_t c = (i / 2) * 4 * kWave + 4 * lane + 2 * (i % 2);
-    if (i / 2 < nv && c < sh.C) stale |= 1u << i;
-  }
-  uint32_t spins = 0;
-  while (true) {
-    uint32_t still = 0;
+  for (uint32_t h = 0; h < 2; ++h) {
+    if (h * kManyNV / 2 < nv) {
+      uint64_t raw[kManyNV];
 #pragma unroll
-    for (uint32_t i = 0; i < 2 * kManyNV; ++i) {
-      if (stale & (1u << i)) {
-        const uint32_t c = (i / 2) * 4 * kWave + 4 * lane + 2 * (i % 2);
-        const uint64_t r = load_word(src + c / 2);
-        const bool ok0 = (uint32_t)(r >> 16) % 65536u == tag;
-        const bool ok1 = c + 1 >= sh.C || (uint32_t)(r >> 48) == tag;
-        if (ok0 && ok1) {
-          const uint64_t v = (r & 0xFFFFull) | (c + 1 < sh.C ? ((r >> 32) & 0xFFFFull) << 16 : 0ull);
-          ev[i / 2] |= v << (32 * (i % 2));
-        } else {
-          still |= 1u << i;
+      for (uint32_t j = 0; j < kManyNV; ++j) {
+        const uint32_t i = h * kManyNV + j, c = pair_col(i);
+        raw[j] = (i / 2 < nv && c < sh.C) ? load_word(src + c / 2) : 0ull;
+      }
+#pragma unroll
+      for (uint32_t j = 0; j < kManyNV; ++j) {
+        const uint32_t i = h * kManyNV + j, c = pair_col(i);
+        if (i / 2 < nv && c < sh.C) {
+          if (fresh(raw[j], c)) fold(raw[j], i, c);
+          else stale |= 1u << i;
         }
       }
     }
-    stale = still;
-    if (!__any(stale != 0)) break;
-    if (++spins > a.spin_limit || ((spins & 63u) == 0 && load_tagged(a.err) != 0)) return false;
+  }
+  uint32_t spins = 0;
+  while (__any(stale != 0)) {
+    if (++spins > a.spin_limit || ((spins & 63u) == 0 && load_entry(gbl(a.err)) != 0))
+      return false;
     __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+    for (uint32_t i = 0; i < 2 * kManyNV; ++i) {
+      if (stale & (1u << i)) {
+        const uint32_t c = pair_col(i);
+        const uint64_t r = load_word(src + c / 2);
+        if (fresh(r, c)) {
+          fold(r, i, c);
+          stale &= ~(1u << i);
+        }
+      }
+    }
   }
   uint32_t c_hi;
   const uint32_t T = topk_threshold(ev, sh.S, sh.k, in.guess, &c_hi);
@@ -245,7 +304,9 @@ __device__ bool topk_step(const ManyArgs& a, ManyInst& in, uint32_t t, uint32_t 
 
   // Winners word by word: every field above T, and the first `need` fields
   // equal to T in column order; ranks by prefix counts over the lanes.
-  int32_t* wrow = in.win_out + (size_t)t * sh.k;
+  HTMSP_G int32_t* wrow = gbl(in.win_out + (size_t)t * sh.k);
+  HTMSP_G int32_t* ovrow = in.ov_out ? gbl(in.ov_out + (size_t)t * sh.C) : nullptr;
+  HTMSP_G uint32_t* hist = in.hist ? gbl(in.hist) : nullptr;
   const uint64_t k_gt = (uint64_t)(0x8000u - (T + 1)) * kOnes16;
   const uint64_t k_ge = (uint64_t)(0x8000u - T) * kOnes16;
   uint32_t eq_before = 0, sel_before = 0, clast1 = 0;
@@ -276,11 +337,10 @@ __device__ bool topk_step(const ManyArgs& a, ManyInst& in, uint32_t t, uint32_t 
           wrow[pos] = (int32_t)c;
           ++pos;
           // this wave is the instance's only histogram writer in the launch
-          if (in.hist) in.hist[c] += 1u;
+          if (hist) hist[c] += 1u;
         }
         if (take & (0x8000ull << (16 * q))) clast1 = max(clast1, c + 1);
-        if (in.ov_out && c < sh.C)
-          in.ov_out[(size_t)t * sh.C + c] = (int32_t)((ev[u] >> (16 * q)) & 0xFFFFu);
+        if (ovrow && c < sh.C) ovrow[c] = (int32_t)((ev[u] >> (16 * q)) & 0xFFFFu);
       }
       sel_before += wave_count<3>(n);
     }
@@ -289,7 +349,7 @@ __device__ bool topk_step(const ManyArgs& a, ManyInst& in, uint32_t t, uint32_t 
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) clast1 = max(clast1, (uint32_t)__shfl_xor(clast1, off));
   if (lane == 0)
-    store_word64(in.dec, ((uint64_t)tag << 48) | ((uint64_t)T << 32) | (uint64_t)clast1);
+    store_word64(gbl(in.dec), ((uint64_t)tag << 48) | ((uint64_t)T << 32) | (uint64_t)clast1);
   return true;
 }
 
@@ -307,18 +367,21 @@ __global__ __launch_bounds__(kManyThreads, 2) void k_sp_many(ManyArgs a) {
   for (uint32_t i = threadIdx.x; i < kTileColumns; i += kManyThreads) L.cnt[i] = 0;
   if (threadIdx.x == 0) s_ok[0] = s_ok[1] = 1;
   __syncthreads();
-  const uint32_t t0 = a.task_off[blockIdx.x], t1 = a.task_off[blockIdx.x + 1];
+  const HTMSP_G uint32_t* task_off = gbl(a.task_off);
+  const uint32_t t0 = task_off[blockIdx.x], t1 = task_off[blockIdx.x + 1];
   bool ok = true;
   for (uint32_t t = 0; t <= a.Fmax && ok; ++t) {
     for (uint32_t j = t0; j < t1 && ok; ++j) {
-      const ManyTask task = a.tasks[j];
-      ManyInst& in = a.insts[task.inst];
+      const ManyTask task = load_desc(a.tasks + j);
+      // a copy in registers; the top-k task writes back its guess
+      ManyInst in = load_desc(a.insts + task.inst);
       if (t > in.F) continue;
       if (task.kind == 0) {
         // the host deals at most kMaxTileSlots tiles, first, to a workgroup
         ok = j - t0 < kMaxTileSlots && tile_step<ALIGNED>(a, in, task.c0, task.c1, t, j - t0, L);
       } else if (t < in.F && wave == 0) {
         ok = topk_step(a, in, t, lane);
+        if (lane == 0) *gbl(&a.insts[task.inst].guess) = in.guess;
       }
     }
     // a failed top-k task (wave 0 only) ends the whole workgroup
@@ -326,7 +389,7 @@ __global__ __launch_bounds__(kManyThreads, 2) void k_sp_many(ManyArgs a) {
     __syncthreads();
     ok = s_ok[t & 1] != 0;
   }
-  if (!ok && threadIdx.x == 0) store_tagged(a.err, 1u);
+  if (!ok && threadIdx.x == 0) store_entry(gbl(a.err), 1u);
 }
 
 }  // namespace

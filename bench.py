@@ -219,7 +219,7 @@ def bench_infer(args, torch, sp, synth):
     abytes = algorithmic_bytes_infer(cfg, F)
     achieved = abytes / (call_ms * 1e-3) / 1e9
     traffic, traffic_bytes = measured_traffic("k_infer_gather_960x540_1024c_256s.md",
-                                              "k_infer_gather+k_topk_batch",
+                                              "k_infer_gather_db+k_topk_batch",
                                               call_ms)
 
     # the same frames one launch sequence at a time, and through the
@@ -254,7 +254,7 @@ def bench_infer(args, torch, sp, synth):
         "synapse_updates_per_s": fps * C * S,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_infer_gather + k_topk_batch", "kernel_ms_per_launch": call_ms,
+                     "kernel": "k_infer_gather_db + k_topk_batch", "kernel_ms_per_launch": call_ms,
                      "algorithmic_bytes_per_launch": abytes,
                      "counter_bytes_per_launch": traffic_bytes},
         **comp,

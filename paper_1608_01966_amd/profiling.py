@@ -29,6 +29,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = {
     "k_sp_persistent": ("sp_kernels.hip", "sp_device.h", "sp_internal.h"),
     "k_infer_gather": ("sp_infer.hip", "sp_device.h", "sp_internal.h"),
+    "k_infer_gather_db": ("sp_infer.hip", "sp_device.h", "sp_internal.h"),
     "k_topk_batch": ("sp_infer.hip", "sp_device.h", "sp_internal.h"),
     "k_sp_many": ("sp_many.hip", "sp_device.h", "sp_internal.h"),
     "k_encode": ("sp_encode.hip", "sp_device.h", "sp_internal.h"),

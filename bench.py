@@ -486,6 +486,72 @@ def bench_local(args, torch, sp, synth):
     }
 
 
+def bench_boost(args, torch, sp, synth):
+    """Learning with boosting and duty cycles: 960x540 blob frames, 1024
+    columns x 256 synapses, 40 winners, duty-cycle period 1024, minimum duty
+    0.01 of the maximum, boost up to 10, permanence raise 13/256."""
+    F = args.local_frames
+    w = synth.workload_paper_scale(frames=F, columns=1024, synapses=256)
+    cfg = w.cfg
+    bc = {"period_log2": 10, "min_pct_q16": 655, "max_boost_q8": 2560, "bump_q8": 13}
+    C, S, k = cfg["num_columns"], cfg["synapses_per_column"], cfg["winners"]
+    pool = sp.SpatialPooler(cfg, w.idx, w.perm)
+    perm0 = pool.perm.clone()
+    frames = torch.from_numpy(w.frames.view(np.int32)).cuda()
+    win = torch.empty((F, k), dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def run(ev0=None, ev1=None):
+        pool.perm.copy_(perm0)
+        sp.sp_boost_reset(pool.handle, stream)
+        if ev0 is not None:
+            ev0.record(stream)
+        sp.sp_step_boost(pool.handle, cfg, bc, frames, True, None, win, stream)
+        if ev1 is not None:
+            ev1.record(stream)
+
+    for _ in range(args.warmup):
+        run()
+    pool.sync()
+    warm_clock(lambda: (run(), pool.sync()), args.warm_seconds)
+    wall_s, call_ms = timed(run, args.steps)
+    pool.sync()
+    fps = args.steps * F / wall_s
+    abytes = algorithmic_bytes_learn(cfg, win.cpu().numpy()) + F * 12 * C
+    achieved = abytes / (call_ms * 1e-3) / 1e9
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        n, dt = 8, 0.0
+        while True:
+            t0 = time.perf_counter()
+            oracle.run_boost(cfg, bc, w.idx, w.perm, w.frames[:n], want_overlaps=False)
+            dt = time.perf_counter() - t0
+            if dt > args.cpu_budget / 3 or n >= F:
+                break
+            n = min(2 * n, F)
+        cpu = {"value": n / dt, "unit": "frames/s", "cores": 1, "kind": "oracle",
+               "sample": f"first {n} frames from the same state, {dt:.2f} s single-threaded"}
+    return {
+        "metric": "SP frames/s with boosting and duty cycles (1024 columns x 256 synapses, "
+                  "learning on)",
+        "value": fps, "unit": "frames/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall_s / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": f"960x540 blob frames, 1024 columns x 256 synapses, 40 winners, "
+                               f"duty period 1024, min duty 0.01, max boost 10, raise 13/256, "
+                               f"{F} sequential learning frames per step",
+                   "frames_per_step": F, "path": "boost"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_overlap_plain + k_topk_plain + k_learn_plain + k_boost_update",
+                     "kernel_ms_per_launch": call_ms, "algorithmic_bytes_per_launch": abytes,
+                     "counter_bytes_per_launch": None},
+        "cpu_baseline": cpu,
+    }
+
+
 def bench_serve(args, torch, sp, synth):
     from paper_1608_01966_amd import serve
     P = args.pool_frames
@@ -548,7 +614,7 @@ def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload",
-                    choices=["learn", "infer", "multi", "serve", "encode", "local"],
+                    choices=["learn", "infer", "multi", "serve", "encode", "local", "boost"],
                     default="learn")
     ap.add_argument("--local-frames", type=int, default=200)
     ap.add_argument("--encode-frames", type=int, default=256)
@@ -598,7 +664,8 @@ def main() -> int:
         del src, dst
 
     fn = {"learn": bench_learn, "infer": bench_infer, "multi": bench_multi,
-          "serve": bench_serve, "encode": bench_encode, "local": bench_local}[args.workload]
+          "serve": bench_serve, "encode": bench_encode, "local": bench_local,
+          "boost": bench_boost}[args.workload]
     line = fn(args, torch, sp, synth)
     print(json.dumps(line), flush=True)
     return 0

@@ -414,50 +414,67 @@ __global__ __launch_bounds__(128) void k_sp_persistent(PersistArgs a) {
     }
   };
 
-  uint32_t prev_t = 0;
-  bool prev_two = false;
-  for (uint32_t t = 0; t < a.F; t += 2) {
-    const bool two = t + 1 < a.F;
+  // Input words of frames [t, t + nf) from the producer's ring.
+  auto load_pair = [&](uint32_t t, bool two, uint32_t (&x0)[ROWS], uint32_t (&x1)[ROWS]) {
     const uint32_t nf = two ? 2u : 1u;
-    // Input words of the pair's frames from the producer.
-    {
-      uint32_t spins = 0;
-      while (lds_acquire(&ctl[0]) < t + nf) {
-        if (lds_acquire(&ctl[2]) != 0 || ++spins > a.spin_limit) {
-          abort = true;
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-      }
+    uint32_t spins = 0;
+    while (lds_acquire(&ctl[0]) < t + nf) {
+      if (lds_acquire(&ctl[2]) != 0 || ++spins > a.spin_limit) return false;
+      __builtin_amdgcn_s_sleep(1);
     }
-    if (abort) break;
-    uint32_t w0[ROWS], w1[ROWS];
-    {
-      const uint32_t* s0 = ring + (t % kRing) * ROWS * kWave + lane;
-      const uint32_t* s1 = ring + ((t + 1) % kRing) * ROWS * kWave + lane;
-#pragma unroll
-      for (uint32_t r = 0; r < ROWS; ++r) {
-        w0[r] = s0[r * kWave];
-        w1[r] = two ? s1[r * kWave] : 0u;
-      }
-    }
-    lds_release(&ctl[1], t + nf);
-
-    // Frame t's overlaps; frame t + 1's if each column loses frame t (same
-    // state) and if it wins it (state after learning frame t).
-    uint32_t ov0[CPW], ovL[CPW], ovW[CPW];
-    uint32_t stW[ROWS], mskW[ROWS];
-    group_overlaps<RPC, CPW, ROWS>(w0, msk, ncols, sh.m, ov0);
+    const uint32_t* s0 = ring + (t % kRing) * ROWS * kWave + lane;
+    const uint32_t* s1 = ring + ((t + 1) % kRing) * ROWS * kWave + lane;
 #pragma unroll
     for (uint32_t r = 0; r < ROWS; ++r) {
-      const uint32_t i = st[r] >> 9;
-      const uint32_t q = learn_q(st[r] & 511u, input_bit(w0[r], i), sh);
-      const bool ok = a.learn && ((row_ok >> r) & 1u);  // no learning: both cases agree
-      stW[r] = ok ? (i << 9) | q : st[r];
-      mskW[r] = ok ? (q >= sh.theta ? 1u << (i & 31u) : 0u) : msk[r];
+      x0[r] = s0[r * kWave];
+      x1[r] = two ? s1[r * kWave] : 0u;
     }
-    group_overlaps<RPC, CPW, ROWS>(w1, msk, ncols, sh.m, ovL);
-    group_overlaps<RPC, CPW, ROWS>(w1, mskW, ncols, sh.m, ovW);
+    lds_release(&ctl[1], t + nf);
+    return true;
+  };
+
+  // What a pair publishes, for the columns in `cols` (a mask of own columns):
+  // frame t's overlap; the state after learning frame t; frame t + 1's
+  // overlap if the column loses frame t (same state) and if it wins it.
+  auto products = [&](uint32_t cols, const uint32_t (&x0)[ROWS], const uint32_t (&x1)[ROWS],
+                      uint32_t (&o0)[CPW], uint32_t (&oL)[CPW], uint32_t (&oW)[CPW],
+                      uint32_t (&sW)[ROWS], uint32_t (&mW)[ROWS]) {
+#pragma unroll
+    for (uint32_t j = 0; j < CPW; ++j) {
+      if ((cols >> j) & 1u) {
+        uint32_t r0 = 0, rL = 0, rW = 0;
+#pragma unroll
+        for (uint32_t rr = 0; rr < RPC; ++rr) {
+          const uint32_t r = j * RPC + rr;
+          const uint32_t i = st[r] >> 9;
+          const uint32_t q = learn_q(st[r] & 511u, input_bit(x0[r], i), sh);
+          const bool ok = a.learn && ((row_ok >> r) & 1u);  // no learning: both cases agree
+          sW[r] = ok ? (i << 9) | q : st[r];
+          mW[r] = ok ? (q >= sh.theta ? 1u << (i & 31u) : 0u) : msk[r];
+          r0 += (uint32_t)__popcll(__ballot((x0[r] & msk[r]) != 0u));
+          rL += (uint32_t)__popcll(__ballot((x1[r] & msk[r]) != 0u));
+          rW += (uint32_t)__popcll(__ballot((x1[r] & mW[r]) != 0u));
+        }
+        const bool live = j < ncols;
+        o0[j] = (live && r0 >= sh.m) ? r0 : 0u;
+        oL[j] = (live && rL >= sh.m) ? rL : 0u;
+        oW[j] = (live && rW >= sh.m) ? rW : 0u;
+      }
+    }
+  };
+
+  constexpr uint32_t kAllCols = (1u << CPW) - 1u;
+  uint32_t w0[ROWS], w1[ROWS];       // the pair's input words
+  uint32_t ov0[CPW], ovL[CPW], ovW[CPW];
+  uint32_t stW[ROWS], mskW[ROWS];
+  uint32_t prev_t = 0;
+  bool prev_two = false;
+  if (a.F > 0) {
+    abort = !load_pair(0, a.F > 1, w0, w1);
+    if (!abort) products(kAllCols, w0, w1, ov0, ovL, ovW, stW, mskW);
+  }
+  for (uint32_t t = 0; t < a.F && !abort; t += 2) {
+    const bool two = t + 1 < a.F;
 
     // Publish into every replica.
     const uint32_t g = a.frame_base + t / 2;
@@ -483,6 +500,24 @@ __global__ __launch_bounds__(128) void k_sp_persistent(PersistArgs a) {
       write_frame(a, ev0, r0, prev_t, lane, mine, c_begin);
       if (prev_two) write_frame(a, ev1, r1, prev_t + 1, lane, mine, c_begin);
     }
+
+    // Speculation while the exchange is in flight: the next pair's products
+    // with the current state, which stays right for every own column that
+    // wins neither frame of this pair (most of them); the others are redone
+    // once this pair's winners are known.
+    const uint32_t tn = t + 2;
+    const bool has_next = tn < a.F, two_next = tn + 1 < a.F;
+    uint32_t n0[ROWS], n1[ROWS];
+    uint32_t sov0[CPW], sovL[CPW], sovW[CPW];
+    uint32_t sstW[ROWS], smskW[ROWS];
+    if (has_next) {
+      if (!load_pair(tn, two_next, n0, n1)) {
+        abort = true;
+        break;
+      }
+      products(kAllCols, n0, n1, sov0, sovL, sovW, sstW, smskW);
+    }
+
     {
       uint32_t spins = 0;
       while (true) {
@@ -540,28 +575,54 @@ __global__ __launch_bounds__(128) void k_sp_persistent(PersistArgs a) {
       if (T1) guess = T1;
     }
 
-    // Learning: columns that won frame t take the state learned from it,
-    // then columns that win frame t + 1 learn from that frame.
+    // Learning, on the own columns that won: those that won frame t take the
+    // state learned from it, then those that win frame t + 1 learn from it.
+    uint32_t changed = 0;
     if (a.learn) {
-      const uint64_t sel0 = __ballot(r0.sel);
-      const uint64_t sel1 = two ? __ballot(r1.sel) : 0ull;
+      const uint32_t sel0 = (uint32_t)__ballot(r0.sel) & kAllCols;
+      const uint32_t sel1 = two ? (uint32_t)__ballot(r1.sel) & kAllCols : 0u;
+      changed = sel0 | sel1;
 #pragma unroll
-      for (uint32_t r = 0; r < ROWS; ++r) {
-        const uint32_t j = r / RPC;
-        const bool won0 = (sel0 >> j) & 1ull;
-        st[r] = won0 ? stW[r] : st[r];
-        msk[r] = won0 ? mskW[r] : msk[r];
-        if ((sel1 >> j) & 1ull) {
-          const uint32_t i = st[r] >> 9;
-          const uint32_t q = learn_q(st[r] & 511u, input_bit(w1[r], i), sh);
-          const bool ok = (row_ok >> r) & 1u;
-          st[r] = ok ? (i << 9) | q : st[r];
-          msk[r] = ok ? (q >= sh.theta ? 1u << (i & 31u) : 0u) : msk[r];
+      for (uint32_t j = 0; j < CPW; ++j) {
+        if ((changed >> j) & 1u) {
+#pragma unroll
+          for (uint32_t rr = 0; rr < RPC; ++rr) {
+            const uint32_t r = j * RPC + rr;
+            if ((sel0 >> j) & 1u) {
+              st[r] = stW[r];
+              msk[r] = mskW[r];
+            }
+            if ((sel1 >> j) & 1u) {
+              const uint32_t i = st[r] >> 9;
+              const uint32_t q = learn_q(st[r] & 511u, input_bit(w1[r], i), sh);
+              const bool ok = (row_ok >> r) & 1u;
+              st[r] = ok ? (i << 9) | q : st[r];
+              msk[r] = ok ? (q >= sh.theta ? 1u << (i & 31u) : 0u) : msk[r];
+            }
+          }
         }
       }
     }
     prev_t = t;
     prev_two = two;
+
+    // The next pair: the speculation, redone for the columns that learned.
+    if (has_next) {
+      if (changed) products(changed, n0, n1, sov0, sovL, sovW, sstW, smskW);
+#pragma unroll
+      for (uint32_t r = 0; r < ROWS; ++r) {
+        w0[r] = n0[r];
+        w1[r] = n1[r];
+        stW[r] = sstW[r];
+        mskW[r] = smskW[r];
+      }
+#pragma unroll
+      for (uint32_t j = 0; j < CPW; ++j) {
+        ov0[j] = sov0[j];
+        ovL[j] = sovL[j];
+        ovW[j] = sovW[j];
+      }
+    }
   }
 
   if (abort) {

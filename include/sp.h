@@ -232,7 +232,7 @@ int sp_step_local(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames,
  * image, and the mean rounded half up. */
 typedef struct sp_encoder_config {
   uint32_t width, height; /* input frame size in pixels                        */
-  uint32_t factor;        /* reduction factor >= 1 (1 = none); output is        */
+  uint32_t factor;        /* reduction factor 1..32 (1 = none); output is       */
                           /* (width / factor) x (height / factor), at most 4096 */
                           /* pixels wide                                        */
   uint32_t block;         /* odd window size, 3..11                             */
@@ -246,7 +246,8 @@ size_t sp_encoded_bits(const sp_encoder_config* cfg);
 /* Encodes num_frames frames.  rgb_dev: device bytes [num_frames][height]
  * [width][3] (R, G, B).  frames_dev: device words [num_frames][ceil(bits /
  * 32)] in the layout sp_step reads (pixel p = y w + x at bit p & 31 of word
- * p >> 5, trailing bits zero).  Asynchronous on `stream`; allocates nothing.
+ * p >> 5, trailing bits zero); the call clears it first.  Asynchronous on
+ * `stream`; allocates nothing.
  * SP_EINVAL on a bad configuration or pointer. */
 int sp_encode(const sp_encoder_config* cfg, const uint8_t* rgb_dev, uint32_t num_frames,
               uint32_t* frames_dev, void* stream);

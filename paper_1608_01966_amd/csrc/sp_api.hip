@@ -648,12 +648,9 @@ int sp_step_many(sp_handle* const* hs, uint32_t n, const uint32_t* const* frames
 
 namespace {
 
-// Tile of about 8 output rows (fewer for wide frames), a multiple of 64
-// pixels, whose LDS (gray rows with halo, vertical sums) fits 64 KB so that
-// two workgroups share a CU; 0 when even one row does not fit.
 int encoder_shape(const sp_encoder_config* c, htmsp::EncShape* e) {
   if (!c) return fail(SP_EINVAL, "encoder config is NULL");
-  if (c->factor < 1) return fail(SP_EINVAL, "factor must be >= 1");
+  if (c->factor < 1 || c->factor > 32) return fail(SP_EINVAL, "factor=%u outside 1..32", c->factor);
   if (c->block < 3 || c->block > 11 || c->block % 2 == 0)
     return fail(SP_EINVAL, "block=%u must be odd in 3..11", c->block);
   if (c->offset < -255 || c->offset > 255)
@@ -672,22 +669,9 @@ int encoder_shape(const sp_encoder_config* c, htmsp::EncShape* e) {
   e->w = w;
   e->h = h;
   e->words = (uint32_t)(((uint64_t)w * h + 31) / 32);
-  const uint32_t r = c->block / 2;
-  for (uint32_t rows : {8u, 4u, 2u, 1u}) {
-    const uint32_t tile = std::max<uint32_t>(64u, rows * w / 64 * 64);
-    const uint32_t vrows = (tile + w - 1) / w + 1, grows = vrows + 2 * r;
-    const uint32_t gray = (uint32_t)align_up((size_t)grows * w, 4);
-    const uint32_t lds = gray + vrows * w * 4;
-    if (lds <= 65536 || rows == 1) {
-      if (lds > 160 * 1024) return fail(SP_EINVAL, "encoded width %u too large", w);
-      e->tile_px = tile;
-      e->tiles = (uint32_t)(((uint64_t)w * h + tile - 1) / tile);
-      e->gray_bytes = gray;
-      e->lds_bytes = lds;
-      return SP_OK;
-    }
-  }
-  return fail(SP_EINVAL, "encoder tiling failed");
+  e->area = c->factor * c->factor;
+  e->area_magic = (uint32_t)(((1ull << 32) + e->area - 1) / e->area);
+  return SP_OK;
 }
 
 }  // namespace

@@ -9,13 +9,18 @@
 // edge pixels repeated outside the image, mean rounded half up, on iff
 // gray > mean - offset; pixel p = y w + x at bit p & 31 of word p >> 5.
 //
-// One workgroup per (frame, tile): a tile is a 64-pixel-aligned run of about
-// kTileRows output rows in row-major order.  The workgroup builds the gray
-// rows the tile needs (plus r = b/2 halo rows) in LDS straight from the RGB
-// frame, the vertical window sums of the tile's rows next, and finally the
-// horizontal sums, the threshold and the packing by 64-lane ballots.  Tiles
-// of one frame get block ids equal modulo 8 (one XCD), so the halo rows two
-// tiles share are read from device memory once.
+// One workgroup per (frame, band of kBandRows output rows, strip of
+// 256 - 2r output columns).  Each thread owns one column of the strip plus
+// its r halo columns on either side and walks down the band: it computes
+// the gray value of each input row it needs straight from the RGB frame,
+// keeps the last b of them in registers and forms the vertical window sum;
+// one LDS row of vertical sums per output row then gives every thread its
+// horizontal window sum.  Threads of halo columns outside the image read the
+// nearest edge column, so border repetition needs no special case.  A
+// 64-lane ballot per row and wave is OR-ed into the (zeroed) output words it
+// covers, which makes any width and strip boundary correct.  Bands of one
+// frame share an XCD (block ids equal modulo 8), so the halo rows two bands
+// both read come from L2.
 #include "sp_device.h"
 #include "sp_internal.h"
 
@@ -26,88 +31,109 @@ namespace {
 using namespace dev;
 
 constexpr uint32_t kEncThreads = 256;
+constexpr uint32_t kBandRows = 32;
 
-__device__ __forceinline__ uint32_t clampu(int v, uint32_t n) {
-  return (uint32_t)min(max(v, 0), (int)n - 1);
+__global__ __launch_bounds__(256) void k_zero(uint32_t* __restrict__ out, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    out[i] = 0u;
 }
 
+template <int B>
 __global__ __launch_bounds__(kEncThreads) void k_encode(const uint8_t* __restrict__ rgb,
                                                         uint32_t F, EncShape e,
                                                         uint32_t* __restrict__ out) {
-  extern __shared__ uint32_t lds[];
-  const uint32_t per = 8 * e.tiles;
+  constexpr int R = B / 2;
+  constexpr uint32_t TW = kEncThreads - 2 * R;  // output columns per strip
+  __shared__ uint32_t vrow[2][kEncThreads];
+  const uint32_t strips = (e.w + TW - 1) / TW;
+  const uint32_t bands = (e.h + kBandRows - 1) / kBandRows;
+  const uint32_t per = 8 * strips * bands;
   const uint32_t f = (blockIdx.x / per) * 8 + blockIdx.x % 8;
-  const uint32_t tile = (blockIdx.x % per) / 8;
+  const uint32_t local = (blockIdx.x % per) / 8;
   if (f >= F) return;  // whole workgroup
+  const uint32_t band = local / strips, strip = local % strips;
   const uint32_t tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
-  const uint32_t w = e.w, h = e.h, r = e.block / 2;
-  const uint32_t p0 = tile * e.tile_px;
-  const uint32_t p1 = min(p0 + e.tile_px, w * h);
-  const uint32_t ya = p0 / w, yb = (p1 - 1) / w;        // output rows of the tile
-  const uint32_t ga = ya >= r ? ya - r : 0u;            // gray rows held
-  const uint32_t gb = min(yb + r, h - 1);
-  const uint32_t grows = gb - ga + 1, vrows = yb - ya + 1;
-  uint8_t* G = reinterpret_cast<uint8_t*>(lds);                          // [grows][w]
-  uint32_t* V = lds + (e.gray_bytes + 3) / 4;                            // [vrows][w]
+  const int x = (int)(strip * TW) - R + (int)tid;  // this thread's column
+  const uint32_t xc = (uint32_t)min(max(x, 0), (int)e.w - 1);
+  const bool out_col = tid >= (uint32_t)R && tid < (uint32_t)R + TW && x < (int)e.w;
+  const uint32_t y0 = band * kBandRows, y1 = min(y0 + kBandRows, e.h);
 
-  // binomial weights (row b - 1 of Pascal's triangle)
-  uint32_t wt[11];
+  // binomial weights, row B - 1 of Pascal's triangle
+  uint32_t wt[B];
   wt[0] = 1;
 #pragma unroll
-  for (uint32_t i = 1; i < 11; ++i) wt[i] = i < e.block ? wt[i - 1] * (e.block - i) / i : 0u;
+  for (int i = 1; i < B; ++i) wt[i] = wt[i - 1] * (B - i) / i;
+  constexpr uint32_t kShift = 2 * (B - 1);
 
-  // Gray rows [ga, gb]: block means of the RGB input, then luma.
   const uint8_t* src = rgb + (size_t)f * e.W * e.H * 3;
-  const uint32_t fa = e.factor, area = fa * fa;
-  for (uint32_t i = tid; i < grows * w; i += kEncThreads) {
-    const uint32_t gy = ga + i / w, gx = i % w;
-    uint32_t R = 0, Gc = 0, B = 0;
-    for (uint32_t dy = 0; dy < fa; ++dy) {
-      const uint8_t* row = src + 3 * ((size_t)(gy * fa + dy) * e.W + gx * fa);
-      for (uint32_t dx = 0; dx < fa; ++dx) {
-        R += row[3 * dx];
-        Gc += row[3 * dx + 1];
-        B += row[3 * dx + 2];
+  const uint32_t fa = e.factor;
+  auto gray = [&](uint32_t gy) {
+    uint32_t r = 0, g = 0, b = 0;
+    if (fa == 1) {
+      const uint8_t* px = src + 3 * ((size_t)gy * e.W + xc);
+      r = px[0];
+      g = px[1];
+      b = px[2];
+    } else {
+      for (uint32_t dy = 0; dy < fa; ++dy) {
+        const uint8_t* row = src + 3 * ((size_t)(gy * fa + dy) * e.W + xc * fa);
+        for (uint32_t dx = 0; dx < fa; ++dx) {
+          r += row[3 * dx];
+          g += row[3 * dx + 1];
+          b += row[3 * dx + 2];
+        }
       }
+      // block means rounded half up; floor(n / area) as a high multiply
+      // (exact for n < 256 area, area <= 1024)
+      const uint32_t half = e.area / 2;
+      r = __umulhi(r + half, e.area_magic);
+      g = __umulhi(g + half, e.area_magic);
+      b = __umulhi(b + half, e.area_magic);
     }
-    R = (R + area / 2) / area;
-    Gc = (Gc + area / 2) / area;
-    B = (B + area / 2) / area;
-    G[i] = (uint8_t)((4899u * R + 9617u * Gc + 1868u * B + 8192u) >> 14);
-  }
-  __syncthreads();
+    return (4899u * r + 9617u * g + 1868u * b + 8192u) >> 14;
+  };
 
-  // Vertical window sums of the tile's rows.
-  for (uint32_t i = tid; i < vrows * w; i += kEncThreads) {
-    const uint32_t y = ya + i / w, x = i % w;
-    uint32_t s = 0;
-    for (uint32_t k = 0; k < e.block; ++k)
-      s += wt[k] * G[(clampu((int)(y + k) - (int)r, h) - ga) * w + x];
-    V[i] = s;
-  }
-  __syncthreads();
-
-  // Horizontal sums, threshold, and packing: 64 consecutive pixels per wave
-  // per round, two output words from one ballot.
-  const uint32_t shift = 2 * (e.block - 1);
-  const uint32_t half = 1u << (shift - 1);
-  for (uint32_t q0 = p0 + kWave * wave; q0 < p1; q0 += kEncThreads) {
-    const uint32_t p = q0 + lane;
+  uint32_t win[B];  // gray values of rows y - R .. y + R of this column
+#pragma unroll
+  for (int i = 0; i < B - 1; ++i) win[i + 1] = gray((uint32_t)min(max((int)y0 - R + i, 0), (int)e.h - 1));
+  uint32_t* dst = out + (size_t)f * e.words;
+  uint32_t buf = 0;
+  for (uint32_t y = y0; y < y1; ++y) {
+#pragma unroll
+    for (int i = 0; i < B - 1; ++i) win[i] = win[i + 1];
+    win[B - 1] = gray((uint32_t)min((int)y + R, (int)e.h - 1));
+    uint32_t v = 0;
+#pragma unroll
+    for (int i = 0; i < B; ++i) v += wt[i] * win[i];
+    vrow[buf][tid] = v;
+    __syncthreads();
     bool on = false;
-    if (p < p1) {
-      const uint32_t y = p / w, x = p % w;
-      const uint32_t* vr = V + (y - ya) * w;
+    if (out_col) {
+      const uint32_t* vr = &vrow[buf][tid - R];
       uint32_t s = 0;
-      for (uint32_t k = 0; k < e.block; ++k)
-        s += wt[k] * vr[clampu((int)(x + k) - (int)r, w)];
-      const int mean = (int)((s + half) >> shift);
-      on = (int)G[(y - ga) * w + x] > mean - e.offset;
+#pragma unroll
+      for (int j = 0; j < B; ++j) s += wt[j] * vr[j];
+      const int mean = (int)((s + (1u << (kShift - 1))) >> kShift);
+      on = (int)win[R] > mean - e.offset;
     }
-    const uint64_t bits = __ballot(on);
-    const uint32_t word = q0 / 32;  // q0 is a multiple of 64
-    uint32_t* dst = out + (size_t)f * e.words;
-    if (lane == 0) dst[word] = (uint32_t)bits;
-    if (lane == 1 && q0 + 32 < p1) dst[word + 1] = (uint32_t)(bits >> 32);
+    uint64_t bits = __ballot(on);
+    // the wave's 64 columns start at xs; output bit y * w + xs + lane
+    int xs = (int)(strip * TW) - R + (int)(kWave * wave);
+    if (xs < 0) {  // first strip: its left halo lanes carry no output
+      bits >>= (uint32_t)(-xs);
+      xs = 0;
+    }
+    if (bits) {
+      const uint64_t base = (uint64_t)y * e.w + (uint32_t)xs;
+      const uint32_t wi = (uint32_t)(base >> 5), o = (uint32_t)(base & 31u);
+      uint32_t part = 0;
+      if (lane == 0) part = (uint32_t)(bits << o);
+      if (lane == 1) part = (uint32_t)(bits >> (32 - o));
+      if (lane == 2 && o) part = (uint32_t)(bits >> (64 - o));
+      if (part && wi + lane < e.words) atomicOr(&dst[wi + lane], part);
+    }
+    buf ^= 1u;
   }
 }
 
@@ -116,15 +142,26 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(const uint8_t* __restric
 hipError_t launch_encode(const uint8_t* rgb, uint32_t F, const EncShape& e, uint32_t* out,
                          hipStream_t s) {
   if (F == 0) return hipSuccess;
-  if (e.lds_bytes > 65536) {
-    hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_encode),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         (int)e.lds_bytes);
-    if (err != hipSuccess) return err;
+  const size_t n = (size_t)F * e.words;
+  size_t zb = (n + 255) / 256;
+  if (zb > 4096) zb = 4096;
+  hipLaunchKernelGGL(k_zero, dim3((uint32_t)zb), dim3(256), 0, s, out, n);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  const uint32_t r = e.block / 2, tw = kEncThreads - 2 * r;
+  const uint32_t strips = (e.w + tw - 1) / tw;
+  const uint32_t bands = (e.h + kBandRows - 1) / kBandRows;
+  const uint32_t blocks = (F + 7) / 8 * 8 * strips * bands;
+#define HTMSP_ENC(B)                                                                      \
+  case B:                                                                                 \
+    hipLaunchKernelGGL(k_encode<B>, dim3(blocks), dim3(kEncThreads), 0, s, rgb, F, e, out); \
+    break;
+  switch (e.block) {
+    HTMSP_ENC(3) HTMSP_ENC(5) HTMSP_ENC(7) HTMSP_ENC(9) HTMSP_ENC(11)
+    default:
+      return hipErrorInvalidValue;
   }
-  const uint32_t groups = (F + 7) / 8 * 8;
-  hipLaunchKernelGGL(k_encode, dim3(groups * e.tiles), dim3(kEncThreads), e.lds_bytes, s, rgb,
-                     F, e, out);
+#undef HTMSP_ENC
   return hipGetLastError();
 }
 

@@ -87,15 +87,13 @@ hipError_t launch_topk_batch(const int32_t* ov, uint32_t F, const Shape& sh, int
                              hipStream_t s);
 
 // Adaptive video encoder (sp_encode.hip).  W x H RGB input, w x h output
-// (w = W / factor, h = H / factor), tiles of tile_px output pixels (a
-// multiple of 64), LDS for the gray halo rows and the vertical sums.
+// (w = W / factor, h = H / factor), `words` per encoded frame; block means
+// use area = factor^2 and area_magic = ceil(2^32 / area) (factor <= 32).
 struct EncShape {
   uint32_t W, H, factor, block;
   int32_t offset;
-  uint32_t w, h, words;       // output size, words per frame
-  uint32_t tile_px, tiles;    // pixels per tile, tiles per frame
-  uint32_t gray_bytes;        // LDS bytes of the gray rows
-  uint32_t lds_bytes;         // total LDS per workgroup
+  uint32_t w, h, words;
+  uint32_t area, area_magic;
 };
 hipError_t launch_encode(const uint8_t* rgb, uint32_t F, const EncShape& e, uint32_t* out,
                          hipStream_t s);

@@ -33,6 +33,7 @@ KERNEL_SOURCES = {
     "k_topk_batch": ("sp_infer.hip", "sp_device.h", "sp_internal.h"),
     "k_sp_many": ("sp_many.hip", "sp_device.h", "sp_internal.h"),
     "k_encode": ("sp_encode.hip", "sp_device.h", "sp_internal.h"),
+    "k_zero": ("sp_encode.hip", "sp_device.h", "sp_internal.h"),
 }
 COPY_KERNEL = "vectorized_elementwise_kernel"
 

@@ -623,7 +623,9 @@ int sp_step_many(sp_handle* const* hs, uint32_t n, const uint32_t* const* frames
       if (num_frames[i1] == 0) continue;
       const uint32_t ct = htmsp::many_tile_columns(hs[i1]->sh.S);
       const size_t nt = (hs[i1]->sh.C + ct - 1) / ct;
-      if (nact_c > 0 && tiles_c + nt > cap) break;
+      if (nact_c > 0 && (tiles_c + nt > cap ||
+                         nact_c + 1 > (size_t)htmsp::kMaxTopkSlots * (size_t)maxb))
+        break;
       tiles_c += nt;
       ++nact_c;
       Fmax_c = std::max(Fmax_c, num_frames[i1]);

@@ -127,6 +127,7 @@ constexpr uint32_t kTileSynapses = 8192;  // synapses per tile task (at most)
 constexpr uint32_t kTileColumns = 1024;   // columns per tile task (at most)
 constexpr uint32_t kManyThreads = 256;
 constexpr uint32_t kMaxTileSlots = 16;    // tile tasks per workgroup (at most)
+constexpr uint32_t kMaxTopkSlots = 8;     // top-k tasks per workgroup (at most)
 
 struct ManyInst {
   const uint32_t* idx;

@@ -359,29 +359,37 @@ __device__ bool topk_step(const ManyArgs& a, ManyInst& in, uint32_t t, uint32_t 
 // path per kernel keeps the register allocation free of spills).
 template <bool ALIGNED>
 __global__ __launch_bounds__(kManyThreads, 2) void k_sp_many(ManyArgs a) {
+  constexpr uint32_t kSlots = kMaxTileSlots + kMaxTopkSlots;
   __shared__ TileLds L;
+  // this workgroup's tasks and their instances, read from device memory once
+  __shared__ ManyTask s_task[kSlots];
+  __shared__ ManyInst s_inst[kSlots];
   // per-step abort flags, alternating so that a flag is never written while
   // a slower thread may still read the previous step's one
   __shared__ uint32_t s_ok[2];
   const uint32_t wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   for (uint32_t i = threadIdx.x; i < kTileColumns; i += kManyThreads) L.cnt[i] = 0;
-  if (threadIdx.x == 0) s_ok[0] = s_ok[1] = 1;
-  __syncthreads();
   const HTMSP_G uint32_t* task_off = gbl(a.task_off);
   const uint32_t t0 = task_off[blockIdx.x], t1 = task_off[blockIdx.x + 1];
-  bool ok = true;
+  // the host deals at most kMaxTileSlots tiles, first, and kMaxTopkSlots
+  // top-k tasks to a workgroup
+  const uint32_t nt = min(t1 - t0, kSlots);
+  for (uint32_t i = threadIdx.x; i < nt; i += kManyThreads) {
+    s_task[i] = load_desc(a.tasks + t0 + i);
+    s_inst[i] = load_desc(a.insts + s_task[i].inst);
+  }
+  if (threadIdx.x == 0) s_ok[0] = s_ok[1] = t1 - t0 <= kSlots ? 1u : 0u;
+  __syncthreads();
+  bool ok = s_ok[0] != 0;
   for (uint32_t t = 0; t <= a.Fmax && ok; ++t) {
-    for (uint32_t j = t0; j < t1 && ok; ++j) {
-      const ManyTask task = load_desc(a.tasks + j);
-      // a copy in registers; the top-k task writes back its guess
-      ManyInst in = load_desc(a.insts + task.inst);
+    for (uint32_t j = 0; j < nt && ok; ++j) {
+      const ManyTask& task = s_task[j];
+      ManyInst& in = s_inst[j];  // the top-k task keeps its guess here
       if (t > in.F) continue;
       if (task.kind == 0) {
-        // the host deals at most kMaxTileSlots tiles, first, to a workgroup
-        ok = j - t0 < kMaxTileSlots && tile_step<ALIGNED>(a, in, task.c0, task.c1, t, j - t0, L);
+        ok = j < kMaxTileSlots && tile_step<ALIGNED>(a, in, task.c0, task.c1, t, j, L);
       } else if (t < in.F && wave == 0) {
         ok = topk_step(a, in, t, lane);
-        if (lane == 0) *gbl(&a.insts[task.inst].guess) = in.guess;
       }
     }
     // a failed top-k task (wave 0 only) ends the whole workgroup

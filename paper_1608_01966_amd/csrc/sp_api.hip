@@ -286,16 +286,17 @@ int many_slot(int device, size_t bytes, ManySlot** out) {
 }
 
 // One cooperative launch over hs[0..n) (instances with frames; the caller
-// holds g_many_mu).  Tiles are dealt round-robin over the workgroups, top-k
-// tasks from the last workgroup backwards, so that in each workgroup tiles
-// come before top-k tasks and no workgroup holds more than kMaxTileSlots
-// tiles (tiles <= kMaxTileSlots * maxb).
+// holds g_many_mu).  The first workgroups hold tile tasks only, dealt
+// round-robin, at most kMaxTileSlots each; the last many_topk_blocks()
+// hold the top-k tasks only, also round-robin.
 int many_launch(sp_handle* const* hs, uint32_t n, const uint32_t* const* frames_dev,
                 const uint32_t* num_frames, int learn, int32_t* const* overlaps_dev,
                 int32_t* const* winners_dev, hipStream_t s, int dev, int maxb, bool aligned,
                 size_t ntiles, uint32_t nact, uint32_t Fmax, uint32_t* err) {
   const uint32_t ntasks = (uint32_t)(ntiles + nact);
-  const uint32_t grid = std::min<uint32_t>(ntasks, (uint32_t)maxb);
+  const uint32_t kblocks = htmsp::many_topk_blocks(nact, (size_t)maxb);
+  const uint32_t tblocks = (uint32_t)std::min<size_t>(ntiles, (size_t)maxb - kblocks);
+  const uint32_t grid = tblocks + kblocks;
   std::vector<std::vector<htmsp::ManyTask>> per(grid);
   std::vector<htmsp::ManyInst> insts;
   insts.reserve(nact);
@@ -321,10 +322,10 @@ int many_launch(sp_handle* const* hs, uint32_t n, const uint32_t* const* frames_
     insts.push_back(in);
     const uint32_t ct = htmsp::many_tile_columns(h->sh.S);
     for (uint32_t c0 = 0; c0 < h->sh.C; c0 += ct)
-      per[next_tile++ % grid].push_back({id, 0u, c0, std::min(h->sh.C, c0 + ct)});
+      per[next_tile++ % tblocks].push_back({id, 0u, c0, std::min(h->sh.C, c0 + ct)});
   }
   for (uint32_t id = 0; id < insts.size(); ++id)
-    per[grid - 1 - (next_topk++ % grid)].push_back({id, 1u, 0u, 0u});
+    per[tblocks + (next_topk++ % kblocks)].push_back({id, 1u, 0u, 0u});
 
   const size_t b_insts = align_up(sizeof(htmsp::ManyInst) * insts.size(), 256);
   const size_t b_tasks = align_up(sizeof(htmsp::ManyTask) * ntasks, 256);
@@ -604,8 +605,10 @@ int sp_step_many(sp_handle* const* hs, uint32_t n, const uint32_t* const* frames
   const int maxb = htmsp::many_max_blocks(dev, aligned);
   if (maxb <= 0) return fail(SP_EDEVICE, "cannot size the many-instance launch");
   // Instances are independent, so they may be split over consecutive
-  // launches: each launch holds at most kMaxTileSlots tiles per workgroup.
-  const size_t cap = (size_t)htmsp::kMaxTileSlots * (size_t)maxb;
+  // launches: each launch holds at most kMaxTileSlots tiles per workgroup,
+  // next to one top-k workgroup per kMaxTopkSlots instances.
+  if (maxb < 2) return fail(SP_EDEVICE, "the many-instance kernel needs two co-resident workgroups");
+  const size_t cap = (size_t)htmsp::kMaxTileSlots * (size_t)(maxb - 1);
   for (uint32_t i = 0; i < n; ++i) {
     const uint32_t ct = htmsp::many_tile_columns(hs[i]->sh.S);
     const size_t nt = (hs[i]->sh.C + ct - 1) / ct;
@@ -623,8 +626,10 @@ int sp_step_many(sp_handle* const* hs, uint32_t n, const uint32_t* const* frames
       if (num_frames[i1] == 0) continue;
       const uint32_t ct = htmsp::many_tile_columns(hs[i1]->sh.S);
       const size_t nt = (hs[i1]->sh.C + ct - 1) / ct;
-      if (nact_c > 0 && (tiles_c + nt > cap ||
-                         nact_c + 1 > (size_t)htmsp::kMaxTopkSlots * (size_t)maxb))
+      // room for the tiles next to the top-k workgroups the instances need
+      const size_t kb = htmsp::many_topk_blocks(nact_c + 1, (size_t)maxb);
+      if (nact_c > 0 &&
+          (kb >= (size_t)maxb || tiles_c + nt > htmsp::kMaxTileSlots * ((size_t)maxb - kb)))
         break;
       tiles_c += nt;
       ++nact_c;

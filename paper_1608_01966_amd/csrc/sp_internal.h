@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 namespace htmsp {
 
 // Shape and learning parameters shared by every kernel, permanences in
@@ -127,7 +129,16 @@ constexpr uint32_t kTileSynapses = 8192;  // synapses per tile task (at most)
 constexpr uint32_t kTileColumns = 1024;   // columns per tile task (at most)
 constexpr uint32_t kManyThreads = 256;
 constexpr uint32_t kMaxTileSlots = 16;    // tile tasks per workgroup (at most)
-constexpr uint32_t kMaxTopkSlots = 8;     // top-k tasks per workgroup (at most)
+constexpr uint32_t kMaxTopkSlots = 32;    // top-k tasks per (top-k) workgroup (at most)
+
+// Top-k workgroups of a many-instance launch over `nact` instances and at
+// most `maxb` co-resident workgroups: one instance per wave while that keeps
+// to an eighth of the grid, more per wave (up to kMaxTopkSlots per
+// workgroup) beyond that.
+inline uint32_t many_topk_blocks(size_t nact, size_t maxb) {
+  const size_t one_per_wave = (nact + 3) / 4, fewest = (nact + kMaxTopkSlots - 1) / kMaxTopkSlots;
+  return (uint32_t)std::min(one_per_wave, std::max(fewest, maxb / 8));
+}
 
 struct ManyInst {
   const uint32_t* idx;

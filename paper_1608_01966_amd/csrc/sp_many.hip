@@ -6,16 +6,17 @@
 // inhibition, the GPU works on the others.
 //
 // Work is split into tasks, assigned statically to the workgroups of a
-// cooperative grid (in each workgroup, tile tasks before top-k tasks):
+// cooperative grid (tile workgroups first, then top-k workgroups):
 //   tile task (instance, columns [c0, c1)), at most kTileSynapses synapses,
-//     the whole workgroup: for step t it applies learning of frame t-1 to its
-//     winning columns, then computes the overlaps of frame t and publishes
-//     them.  Each thread owns up to 32 synapses of the tile's flat
-//     [column][synapse] range and issues all their state loads before the
-//     wait for the previous decision, then both input gathers at once;
-//     per-column counts are summed in LDS, and each tile keeps its last
-//     published overlaps in LDS to decide its winners.
-//   top-k task (instance), wave 0: for step t it collects the instance's
+//     the whole workgroup: once the instance's decision of step t-1 is out,
+//     its step t applies learning of frame t-1 to its winning columns, then
+//     computes the overlaps of frame t and publishes them.  Each thread owns
+//     up to 32 synapses of the tile's flat [column][synapse] range and issues
+//     all their state loads, then both input gathers, at once; per-column
+//     counts are summed in LDS, and each tile keeps its last published
+//     overlaps in LDS to decide its winners.  A workgroup steps whichever of
+//     its tiles is ready.
+//   top-k task (instance), one wave: for step t it collects the instance's
 //     overlaps, resolves the global top-k, writes the frame's outputs (and
 //     adds the winners to the instance's histogram, if it has one) and
 //     publishes a decision word from which every tile derives which of its
@@ -79,23 +80,6 @@ __device__ __forceinline__ void store_entry(HTMSP_G uint32_t* p, uint32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Waits until the instance's decision word carries `tag`; false on abort.
-__device__ bool wait_decision(const ManyInst& in, uint32_t tag, const ManyArgs& a,
-                              uint64_t* out) {
-  uint32_t spins = 0;
-  const HTMSP_G uint64_t* dec = gbl(in.dec);
-  while (true) {
-    const uint64_t d = load_word(dec);
-    if ((uint32_t)(d >> 48) == tag) {
-      *out = d;
-      return true;
-    }
-    if (++spins > a.spin_limit || ((spins & 63u) == 0 && load_entry(gbl(a.err)) != 0))
-      return false;
-    __builtin_amdgcn_s_sleep(1);
-  }
-}
-
 // floor(p / S) for p, S < 2^13 as one high multiply by m = ceil(2^32 / S)
 // (exact there: the rounding error of m, times p, stays below 2^-6); S = 1,
 // where m would not fit, is m = 0.
@@ -106,27 +90,24 @@ __device__ __forceinline__ uint32_t div_s(uint32_t p, uint32_t m) {
 struct TileLds {
   uint32_t cnt[kTileColumns];                 // raw overlap counts of the step
   uint16_t prev[kMaxTileSlots][kTileColumns];  // each tile's published overlaps of the last step
-  uint32_t bc[3];                             // ok, T, last tied winner + 1
 };
 
-// Tile task `slot` of this workgroup, whole workgroup.  Returns false
-// (uniformly) on abort.  ALIGNED (S a multiple of 64): every 64-synapse
-// chunk of a wave lies in one column, so the column, its "won" flag and its
-// count are wave-uniform.
+// Step t of tile task `slot` of this workgroup, whole workgroup, once the
+// scheduler has seen the instance's decision of step t - 1 (T, last tied
+// winner + 1).  ALIGNED (S a multiple of 64): every 64-synapse chunk of a
+// wave lies in one column, so the column, its "won" flag and its count are
+// wave-uniform.
 template <bool ALIGNED>
-__device__ bool tile_step(const ManyArgs& a, const ManyInst& in, uint32_t c0, uint32_t c1,
-                          uint32_t t, uint32_t slot, TileLds& L) {
+__device__ void tile_step(const ManyArgs& a, const ManyInst& in, uint32_t c0, uint32_t c1,
+                          uint32_t t, uint32_t slot, TileLds& L, uint32_t T, uint32_t clast1) {
   const Shape& sh = in.sh;
   const uint32_t tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
-  const uint32_t tag_prev = (in.step_base + t) & 0xFFFFu;  // tag of step t - 1
   const uint32_t tag = (in.step_base + t + 1) & 0xFFFFu;
   const uint32_t ncol = c1 - c0, nsyn = ncol * sh.S;
   const bool learn_now = a.learn && t > 0;
   const bool overlap_now = t < in.F;
   const uint32_t m = in.smagic;
 
-  // The state does not depend on the decision: its loads are in flight
-  // while thread 0 waits.
   const size_t p0 = (size_t)c0 * sh.S;
   const HTMSP_G uint32_t* gidx = gbl(in.idx + p0);
   HTMSP_G float* gperm = gbl(in.perm + p0);
@@ -145,16 +126,6 @@ __device__ bool tile_step(const ManyArgs& a, const ManyInst& in, uint32_t c0, ui
     ix[j] = v ? min(ix[j], sh.N - 1) : 0u;
     q[j] = v ? q[j] : 0u;
   }
-  if (tid == 0) {
-    uint64_t d = 0;
-    const bool ok = t == 0 || wait_decision(in, tag_prev, a, &d);
-    L.bc[0] = ok;
-    L.bc[1] = (uint32_t)(d >> 32) & 0xFFFFu;
-    L.bc[2] = (uint32_t)d;
-  }
-  __syncthreads();
-  if (!L.bc[0]) return false;
-  const uint32_t T = L.bc[1], clast1 = L.bc[2];
   // column cl of this tile won frame t - 1 (its overlap of that frame is the
   // one this tile published last step)
   auto won_col = [&](uint32_t cl) {
@@ -229,7 +200,6 @@ __device__ bool tile_step(const ManyArgs& a, const ManyInst& in, uint32_t c0, ui
       store_entry(gbl(in.ovx) + c0 + cl, (tag << 16) | ov);
     }
   }
-  return true;
 }
 
 // Top-k task, one wave: collects the instance's overlaps of step t, resolves
@@ -238,7 +208,9 @@ __device__ bool tile_step(const ManyArgs& a, const ManyInst& in, uint32_t c0, ui
 // Registers are kept to ev[] plus per-word temporaries past the first
 // collection pass, and the winners are selected word by word while they are
 // written.
-__device__ bool topk_step(const ManyArgs& a, ManyInst& in, uint32_t t, uint32_t lane) {
+// Returns false, having changed nothing, while some overlap of step t is
+// not yet published.
+__device__ bool topk_try(ManyInst& in, uint32_t t, uint32_t lane) {
   const Shape& sh = in.sh;
   const uint32_t tag = (in.step_base + t + 1) & 0xFFFFu;
   const uint32_t nv = (sh.C + 4 * kWave - 1) / (4 * kWave);
@@ -246,9 +218,8 @@ __device__ bool topk_step(const ManyArgs& a, ManyInst& in, uint32_t t, uint32_t 
   uint64_t ev[kManyNV];
 #pragma unroll
   for (uint32_t u = 0; u < kManyNV; ++u) ev[u] = 0;
-  // pair i holds columns c, c + 1 (c = (i / 2) * 256 + 4l + 2 (i % 2)).  The
-  // first pass has every load in flight at once; pairs whose tags are not
-  // yet those of step t are read again, one by one, until they are.
+  // pair i holds columns c, c + 1 (c = (i / 2) * 256 + 4l + 2 (i % 2)); all
+  // loads of a half are in flight at once.
   auto pair_col = [&](uint32_t i) { return (i / 2) * 4 * kWave + 4 * lane + 2 * (i % 2); };
   auto fresh = [&](uint64_t r, uint32_t c) {
     return (uint32_t)(r >> 16) % 65536u == tag && (c + 1 >= sh.C || (uint32_t)(r >> 48) == tag);
@@ -279,23 +250,7 @@ __device__ bool topk_step(const ManyArgs& a, ManyInst& in, uint32_t t, uint32_t 
       }
     }
   }
-  uint32_t spins = 0;
-  while (__any(stale != 0)) {
-    if (++spins > a.spin_limit || ((spins & 63u) == 0 && load_entry(gbl(a.err)) != 0))
-      return false;
-    __builtin_amdgcn_s_sleep(1);
-#pragma unroll
-    for (uint32_t i = 0; i < 2 * kManyNV; ++i) {
-      if (stale & (1u << i)) {
-        const uint32_t c = pair_col(i);
-        const uint64_t r = load_word(src + c / 2);
-        if (fresh(r, c)) {
-          fold(r, i, c);
-          stale &= ~(1u << i);
-        }
-      }
-    }
-  }
+  if (__any(stale != 0)) return false;
   uint32_t c_hi;
   const uint32_t T = topk_threshold(ev, sh.S, sh.k, in.guess, &c_hi);
   const uint32_t need = T ? sh.k - c_hi : 0u;
@@ -357,47 +312,123 @@ __device__ bool topk_step(const ManyArgs& a, ManyInst& in, uint32_t t, uint32_t 
 // already keep more bytes in flight than device memory needs to stream.
 // ALIGNED: every instance of the launch has S a multiple of 64 (one tile
 // path per kernel keeps the register allocation free of spills).
+//
+// A workgroup holds either tile tasks only or top-k tasks only.  A tile
+// workgroup runs whichever of its tiles can take its next step (the
+// instance's decision of the tile's previous step is out), so a tile whose
+// instance is late never holds up the others; thread 0 finds the tile and
+// the whole workgroup runs its step.  In a top-k workgroup every wave polls
+// its own instances (tasks j with j % 4 == wave) and resolves any whose
+// overlaps of its next step are all published.  Both loops end when every
+// task has taken all its steps, or on abort (spin limit or the error word).
 template <bool ALIGNED>
 __global__ __launch_bounds__(kManyThreads, 2) void k_sp_many(ManyArgs a) {
-  constexpr uint32_t kSlots = kMaxTileSlots + kMaxTopkSlots;
+  constexpr uint32_t kSlots = kMaxTopkSlots > kMaxTileSlots ? kMaxTopkSlots : kMaxTileSlots;
   __shared__ TileLds L;
   // this workgroup's tasks and their instances, read from device memory once
   __shared__ ManyTask s_task[kSlots];
   __shared__ ManyInst s_inst[kSlots];
-  // per-step abort flags, alternating so that a flag is never written while
-  // a slower thread may still read the previous step's one
-  __shared__ uint32_t s_ok[2];
-  const uint32_t wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  for (uint32_t i = threadIdx.x; i < kTileColumns; i += kManyThreads) L.cnt[i] = 0;
+  __shared__ uint32_t s_next[kSlots];  // each task's next step
+  __shared__ uint32_t s_pick[4];      // chosen tile, T, last tied winner + 1, status
+  const uint32_t tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
+  for (uint32_t i = tid; i < kTileColumns; i += kManyThreads) L.cnt[i] = 0;
   const HTMSP_G uint32_t* task_off = gbl(a.task_off);
   const uint32_t t0 = task_off[blockIdx.x], t1 = task_off[blockIdx.x + 1];
-  // the host deals at most kMaxTileSlots tiles, first, and kMaxTopkSlots
-  // top-k tasks to a workgroup
   const uint32_t nt = min(t1 - t0, kSlots);
-  for (uint32_t i = threadIdx.x; i < nt; i += kManyThreads) {
+  for (uint32_t i = tid; i < nt; i += kManyThreads) {
     s_task[i] = load_desc(a.tasks + t0 + i);
     s_inst[i] = load_desc(a.insts + s_task[i].inst);
+    s_next[i] = 0;
   }
-  if (threadIdx.x == 0) s_ok[0] = s_ok[1] = t1 - t0 <= kSlots ? 1u : 0u;
   __syncthreads();
-  bool ok = s_ok[0] != 0;
-  for (uint32_t t = 0; t <= a.Fmax && ok; ++t) {
-    for (uint32_t j = 0; j < nt && ok; ++j) {
-      const ManyTask& task = s_task[j];
-      ManyInst& in = s_inst[j];  // the top-k task keeps its guess here
-      if (t > in.F) continue;
-      if (task.kind == 0) {
-        ok = j < kMaxTileSlots && tile_step<ALIGNED>(a, in, task.c0, task.c1, t, j, L);
-      } else if (t < in.F && wave == 0) {
-        ok = topk_step(a, in, t, lane);
+  if (nt == 0) return;  // whole workgroup
+  HTMSP_G uint32_t* err = gbl(a.err);
+
+  if (s_task[0].kind == 1) {
+    // ---- top-k workgroup: each wave on its own instances, no barriers ----
+    bool fail = t1 - t0 > kMaxTopkSlots;
+    uint32_t spins = 0;
+    while (!fail) {
+      bool all_done = true, progress = false;
+      for (uint32_t j = wave; j < nt; j += kManyThreads / kWave) {
+        const uint32_t t = s_next[j];
+        if (t >= s_inst[j].F) continue;
+        all_done = false;
+        if (topk_try(s_inst[j], t, lane)) {
+          s_next[j] = t + 1;  // every lane: each keeps its own view of the slot exact
+          progress = true;
+        }
+      }
+      if (all_done) break;
+      if (progress) {
+        spins = 0;
+      } else {
+        if (++spins > a.spin_limit || ((spins & 63u) == 0 && load_entry(err) != 0)) fail = true;
+        __builtin_amdgcn_s_sleep(1);
       }
     }
-    // a failed top-k task (wave 0 only) ends the whole workgroup
-    if (!ok) s_ok[t & 1] = 0;
-    __syncthreads();
-    ok = s_ok[t & 1] != 0;
+    if (fail && lane == 0) store_entry(err, 1u);
+    return;
   }
-  if (!ok && threadIdx.x == 0) store_entry(gbl(a.err), 1u);
+
+  // ---- tile workgroup ----
+  // Wave 0 looks at every tile at once (lane j: tile j) and takes the first
+  // ready one at or after `rr`, so that no tile is passed over for long.
+  uint32_t rr = 0, spins = 0;
+  while (true) {
+    if (wave == 0) {
+      uint32_t status = 3, pick = 0, T = 0, clast1 = 0;  // 3: nothing ready yet
+      if (t1 - t0 > kMaxTileSlots) {
+        status = 2;
+      } else {
+        const uint32_t j = lane < nt ? lane : 0u;
+        const uint32_t t = s_next[j];
+        const bool live = lane < nt && t <= s_inst[j].F;
+        uint64_t d = 0;
+        if (live && t > 0) d = load_word(gbl(s_inst[j].dec));
+        const bool ready =
+            live && (t == 0 || (uint32_t)(d >> 48) == ((s_inst[j].step_base + t) & 0xFFFFu));
+        const uint64_t lm = __ballot(live), rm = __ballot(ready);
+        if (lm == 0) {
+          status = 1;
+        } else if (rm == 0) {
+          if (++spins > a.spin_limit || ((spins & 63u) == 0 && load_entry(err) != 0))
+            status = 2;
+          else
+            __builtin_amdgcn_s_sleep(1);
+        } else {
+          const uint64_t after = rm & (~0ull << rr);
+          pick = (uint32_t)__ffsll((long long)(after ? after : rm)) - 1;
+          T = (uint32_t)__shfl((int)((uint32_t)(d >> 32) & 0xFFFFu), (int)pick);
+          clast1 = (uint32_t)__shfl((int)(uint32_t)d, (int)pick);
+          status = 0;
+          spins = 0;
+          rr = pick + 1;  // at most kMaxTileSlots < 64
+        }
+      }
+      if (lane == 0) {
+        s_pick[0] = pick;
+        s_pick[1] = T;
+        s_pick[2] = clast1;
+        s_pick[3] = status;
+      }
+    }
+    __syncthreads();
+    const uint32_t status = s_pick[3];
+    if (status == 1) break;
+    if (status == 2) {
+      if (tid == 0) store_entry(err, 1u);
+      break;
+    }
+    if (status == 0) {
+      const uint32_t j = s_pick[0];
+      const ManyTask& task = s_task[j];
+      tile_step<ALIGNED>(a, s_inst[j], task.c0, task.c1, s_next[j], j, L, s_pick[1], s_pick[2]);
+      // every thread has read s_next[j] and s_pick before tile_step's barrier
+      if (tid == 0) s_next[j] += 1;
+    }
+    __syncthreads();
+  }
 }
 
 }  // namespace

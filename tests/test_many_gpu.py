@@ -122,6 +122,29 @@ def test_multi_workload_subset():
     check(synth.workload_multi(64, 12))
 
 
+def test_many_tiny_instances():
+    """600 instances of at most 64 columns: the top-k workgroups then hold
+    several instances per wave."""
+    g = np.random.default_rng(21)
+    ws = []
+    for i in range(600):
+        C = int(g.integers(1, 65))
+        S = int(g.integers(1, 40))
+        cfg = synth.sp_config(int(g.integers(S, 3000)), C, S, int(g.integers(0, 4)),
+                              int(g.integers(1, C + 1)))
+        ws.append(synth.random_instance(3000 + i, cfg, frames=int(g.integers(1, 5)),
+                                        density=float(g.uniform(0.05, 0.4))))
+    check(ws)
+
+
+def test_split_over_launches():
+    """260 instances of 1024 columns x 256 synapses are more tiles than one
+    launch holds, so the call is split; every instance still matches."""
+    ws = [synth.random_instance(4000 + i, synth.sp_config(4096, 1024, 256, 3, 40), 3, 0.1)
+          for i in range(260)]
+    check(ws)
+
+
 def test_same_as_single_instance_step():
     import torch
     w = synth.workload_paper_scale(frames=30, columns=512, synapses=128)

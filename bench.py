@@ -144,10 +144,11 @@ def bench_learn(args, torch, sp, synth):
 
     abytes = algorithmic_bytes_learn(cfg, win.cpu().numpy())
     achieved = abytes / (kernel_ms * 1e-3) / 1e9
+    kname = pool.kernel
     traffic, traffic_bytes = (None, None)
     if (C, S, F) == (1024, 256, 1000):
-        traffic, traffic_bytes = measured_traffic("k_sp_persistent_960x540_1024c_256s.md",
-                                                  "k_sp_persistent", kernel_ms)
+        traffic, traffic_bytes = measured_traffic(f"{kname}_960x540_1024c_256s.md", kname,
+                                                  kernel_ms)
 
     plain = None
     if args.plain_frames > 0:
@@ -177,11 +178,11 @@ def bench_learn(args, torch, sp, synth):
                                f"{F} sequential learning frames per step",
                    "frames_per_step": F, "columns": C, "synapses": S,
                    "input_bits": cfg["input_bits"], "winners": k,
-                   "path": "persistent" if pool.persistent else "plain"},
+                   "path": kname},
         "synapse_updates_per_s": fps * C * S,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_sp_persistent", "kernel_ms_per_launch": kernel_ms,
+                     "kernel": kname, "kernel_ms_per_launch": kernel_ms,
                      "algorithmic_bytes_per_launch": abytes,
                      "counter_bytes_per_launch": traffic_bytes},
         "plain_one_frame_per_launch_frames_per_s": plain,

@@ -38,9 +38,10 @@ struct sp_handle {
   uint32_t many_steps; // steps this handle has taken through sp_step_many
   uint64_t xchg_frames;
   bool persistent;
-  uint32_t grid, replicas;
+  uint32_t grid, block, replicas;
   const void* pkernel;
   size_t plds;
+  int pkind;  // SP_KERNEL_* of the persistent instance
   bool broken;
   int cus;
   // Every learning step and every re-validation changes the state version;
@@ -186,8 +187,9 @@ uint32_t next_pow2(uint32_t x) {
 }
 
 // Chooses the persistent kernel instance: rows of 64 synapses per column
-// rounded up to a power of two, 16 rows per workgroup, exchange words per
-// lane for C; the grid must be co-resident.
+// rounded up to a power of two and exchange words per lane for C; the
+// one-column-group-per-wave kernel when its grid fits one workgroup per CU,
+// else the 16-rows-per-workgroup kernel; the grid must be co-resident.
 void plan_persistent(sp_handle* h) {
   h->persistent = false;
   int dev = h->device, cus = 0, coop = 0;
@@ -199,6 +201,29 @@ void plan_persistent(sp_handle* h) {
     return;
   const uint32_t rpc = next_pow2((sh.S + 63) / 64);
   const uint32_t nv = next_pow2(htmsp::persistent_exchange_entries(sh.C) / 256);
+  // One column group per wave, one workgroup per CU: the fewest rows per
+  // wave (4, 8 or 16, at least one column) that keep the grid to one
+  // workgroup per CU.
+  for (uint32_t rw = std::max(4u, rpc); rw <= 16; rw *= 2) {
+    const uint32_t cols = rw / rpc * htmsp::kPersistWaves;
+    const uint32_t grid = (sh.C + cols - 1) / cols;
+    if (grid > (uint32_t)cus) continue;
+    const void* kw = htmsp::persistent_wave_kernel(rpc, nv, rw);
+    int per_cu = 0;
+    if (kw && hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kw, htmsp::kPersistWaves * 64,
+                                                           0) == hipSuccess &&
+        per_cu >= 1) {
+      h->grid = grid;
+      h->block = htmsp::kPersistWaves * 64;
+      h->replicas = htmsp::kPersistReplicas;
+      h->pkernel = kw;
+      h->plds = 0;
+      h->pkind = SP_KERNEL_PERSISTENT_WAVE;
+      h->persistent = true;
+      return;
+    }
+    break;
+  }
   const uint32_t rows = htmsp::kPersistRows;
   const void* k = htmsp::persistent_kernel(rpc, nv, rows);
   if (!k) return;
@@ -209,9 +234,11 @@ void plan_persistent(sp_handle* h) {
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 128, lds) != hipSuccess) return;
   if ((uint64_t)per_cu * (uint64_t)cus < grid) return;
   h->grid = grid;
+  h->block = 128;
   h->replicas = htmsp::kPersistReplicas;
   h->pkernel = k;
   h->plds = lds;
+  h->pkind = SP_KERNEL_PERSISTENT_GROUP;
   h->persistent = true;
 }
 
@@ -501,7 +528,7 @@ int sp_step(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames, int l
   a.spin_limit = kSpinLimit;
   a.sh = h->sh;
   void* args[] = {&a};
-  hipError_t e = hipLaunchCooperativeKernel(h->pkernel, dim3(h->grid), dim3(128), args,
+  hipError_t e = hipLaunchCooperativeKernel(h->pkernel, dim3(h->grid), dim3(h->block), args,
                                             (unsigned int)h->plds,
                                             static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "persistent step launch");
@@ -866,6 +893,12 @@ int sp_set_histogram(sp_handle* h, uint32_t* hist_dev) {
 int sp_step_is_persistent(const sp_handle* h) {
   if (!h) return fail(SP_EINVAL, "handle is NULL");
   return h->persistent ? 1 : 0;
+}
+
+int sp_step_kernel(const sp_handle* h) {
+  if (!h) return fail(SP_EINVAL, "handle is NULL");
+  if (!h->persistent) return SP_KERNEL_PLAIN;
+  return h->pkind;
 }
 
 int sp_sync(sp_handle* h, void* stream) {

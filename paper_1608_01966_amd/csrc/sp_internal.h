@@ -17,9 +17,9 @@ struct Shape {
   uint32_t theta, inc, dec; // connected threshold, increment, decrement (x256)
 };
 
-// Persistent multi-frame step: one workgroup (a main and a producer wave)
-// per group of `cpw` consecutive columns, each column spread over `rpc`
-// rows of 64 synapses.
+// Persistent multi-frame step (both instances): every column spread over
+// `rpc` rows of 64 synapses, groups of consecutive columns per wave or per
+// workgroup.
 struct PersistArgs {
   const uint32_t* idx;
   float* perm;
@@ -43,10 +43,11 @@ constexpr uint32_t kPersistReplicas = 2;
 
 // LDS of one persistent workgroup holding `rows` rows of 64 synapses.
 size_t persistent_lds_bytes(uint32_t rows);
-// Rows of 64 synapses per persistent workgroup.  Fewer rows (more
-// workgroups) shorten each workgroup's serial chain but multiply the
-// readers of the per-frame exchange; measured at 960x540, 1024 x 256:
-// 4 rows (1024 workgroups) ran 2.7x slower than 16 rows (256 workgroups).
+// Rows of 64 synapses per workgroup of the 16-row instance (a main and a
+// producer wave), used where the column-group-per-wave instance's grid does
+// not fit one workgroup per CU.  Within this instance, fewer rows (more
+// workgroups) multiply the readers of the per-frame exchange; measured at
+// 960x540, 1024 x 256: 4 rows (1024 workgroups) ran 2.7x slower than 16.
 constexpr uint32_t kPersistRows = 16;
 // Exchange arrays per slot (frame t, frame t+1 if lost, frame t+1 if won).
 uint32_t persistent_exchange_arrays();
@@ -57,6 +58,11 @@ uint32_t persistent_exchange_entries(uint32_t C);
 // 64-bit exchange words per lane (1, 2, 4, 8 or 16) and `rows` rows per
 // workgroup (kPersistRows); nullptr otherwise.
 const void* persistent_kernel(uint32_t rpc, uint32_t nv, uint32_t rows);
+// Waves per workgroup of the one-column-group-per-wave kernel.
+constexpr uint32_t kPersistWaves = 4;
+// The one-column-group-per-wave instance for `rpc` rows per column, `nv`
+// exchange words per lane and `rw` rows per wave; nullptr otherwise.
+const void* persistent_wave_kernel(uint32_t rpc, uint32_t nv, uint32_t rw);
 
 hipError_t launch_check_state(const uint32_t* idx, const float* perm, size_t n, uint32_t N,
                               uint32_t* out4, hipStream_t s);

@@ -5,12 +5,15 @@
 // executions are provided:
 //   * plain: three kernels per frame (overlap, global top-k, learning), the
 //     state read from and written to HBM every frame;
-//   * persistent: one cooperative launch for F frames.  Each workgroup keeps
-//     the synapses of its columns in registers for the whole launch, gathers
-//     the input bits of the next frame while it waits, exchanges per-frame
-//     overlaps with all other workgroups through a tagged device buffer, and
-//     resolves the global top-k redundantly so that every workgroup knows
-//     which of its own columns learn, with no second exchange.
+//   * persistent: one cooperative launch for F frames.  The synapses of
+//     every column stay in registers for the whole launch; the input bits of
+//     the next frames are gathered while the exchange is in flight;
+//     per-frame overlaps go to all other workgroups through a tagged device
+//     buffer, and the global top-k is resolved redundantly so that every
+//     wave knows which of its own columns learn, with no second exchange.
+//     Two instances: a column group per wave (k_sp_persistent_w, one
+//     workgroup per CU) and 16 rows per workgroup (k_sp_persistent, for
+//     grids larger than that).
 // Permanences are handled as integers q = 256 * permanence (0..256), so
 // every comparison and update is exact.
 #include "sp_device.h"
@@ -186,7 +189,6 @@ __global__ __launch_bounds__(256) void k_learn_plain(const uint32_t* __restrict_
 // belongs to frame g - 2 with tag (g - 1) & 3 (or is the zeroed initial
 // state), so a stale entry is never taken for a fresh one, and a slot is
 // rewritten only after every workgroup has finished reading it.
-constexpr uint32_t kMaxRows = 16;
 constexpr uint32_t kRing = 8;
 
 __device__ __forceinline__ void lds_release(uint32_t* p, uint32_t v) {
@@ -274,11 +276,11 @@ struct FrameResult {
 template <int NV>
 __device__ __forceinline__ void write_frame(const PersistArgs& a, const uint64_t (&ev)[NV],
                                             const FrameResult& r, uint32_t tt, uint32_t lane,
-                                            bool mine, uint32_t c_begin) {
+                                            bool mine, uint32_t c_begin, bool pad) {
   const Shape& sh = a.sh;
   if (a.ov_out && mine) a.ov_out[(size_t)tt * sh.C + c_begin + lane] = (int32_t)r.ov;
   int32_t* wrow = a.win_out + (size_t)tt * sh.k;
-  if (blockIdx.x == 0)
+  if (pad)
     for (uint32_t i = r.nsel + lane; i < sh.k; i += kWave) wrow[i] = -1;
   if (__ballot(r.sel) != 0ull) {
     const uint32_t gtb = count_ge_before(ev, r.T + 1, lane, c_begin);
@@ -485,20 +487,15 @@ __global__ __launch_bounds__(128) void k_sp_persistent(PersistArgs a) {
     publish(slot, 1, tg, ovL);
     publish(slot, 2, tg, ovW);
 
-    // Collect every column's entries from this XCD's replica; the previous
-    // pair's outputs are written while the first loads are in flight.
+    // The previous pair's outputs, and the next pair's speculation, before
+    // the first read of the exchange: entries are rarely all in before then,
+    // and a read that comes back stale costs a whole further round trip.
     const uint64_t tagw = (uint64_t)tg * kOnes16;
     const uint64_t* xs = x64 + (size_t)(rep * 2 + slot) * NARR * (CPAD / 4);
     uint64_t v0[NV], vL[NV], vW[NV];
-#pragma unroll
-    for (int u = 0; u < NV; ++u) {
-      v0[u] = load_entries(xs + u * kWave + lane);
-      vL[u] = load_entries(xs + CPAD / 4 + u * kWave + lane);
-      vW[u] = load_entries(xs + 2 * (CPAD / 4) + u * kWave + lane);
-    }
     if (t > 0) {
-      write_frame(a, ev0, r0, prev_t, lane, mine, c_begin);
-      if (prev_two) write_frame(a, ev1, r1, prev_t + 1, lane, mine, c_begin);
+      write_frame(a, ev0, r0, prev_t, lane, mine, c_begin, blockIdx.x == 0);
+      if (prev_two) write_frame(a, ev1, r1, prev_t + 1, lane, mine, c_begin, blockIdx.x == 0);
     }
 
     // Speculation while the exchange is in flight: the next pair's products
@@ -518,6 +515,13 @@ __global__ __launch_bounds__(128) void k_sp_persistent(PersistArgs a) {
       products(kAllCols, n0, n1, sov0, sovL, sovW, sstW, smskW);
     }
 
+    // Collect every column's entries from this XCD's replica.
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+      v0[u] = load_entries(xs + u * kWave + lane);
+      vL[u] = load_entries(xs + CPAD / 4 + u * kWave + lane);
+      vW[u] = load_entries(xs + 2 * (CPAD / 4) + u * kWave + lane);
+    }
     {
       uint32_t spins = 0;
       while (true) {
@@ -631,12 +635,354 @@ __global__ __launch_bounds__(128) void k_sp_persistent(PersistArgs a) {
     return;
   }
   if (a.F > 0) {
-    write_frame(a, ev0, r0, prev_t, lane, mine, c_begin);
-    if (prev_two) write_frame(a, ev1, r1, prev_t + 1, lane, mine, c_begin);
+    write_frame(a, ev0, r0, prev_t, lane, mine, c_begin, blockIdx.x == 0);
+    if (prev_two) write_frame(a, ev1, r1, prev_t + 1, lane, mine, c_begin, blockIdx.x == 0);
   }
   if (a.learn) {
 #pragma unroll
     for (uint32_t r = 0; r < ROWS; ++r) {
+      const uint32_t j = r / RPC, s = (r % RPC) * kWave + lane;
+      if ((row_ok >> r) & 1u) a.perm[(size_t)(c_begin + j) * sh.S + s] = q_to_perm(st[r] & 511u);
+    }
+  }
+}
+
+// Persistent multi-frame step, one column group per wave.  The same pair
+// protocol as k_sp_persistent (two frames per exchange, the next pair's
+// products computed while the exchange is in flight), but each workgroup
+// holds kPersistWaves waves and each wave owns CPW = RW / RPC consecutive
+// columns (row r of the wave holds synapses (r % RPC) * 64 + lane of its
+// local column r / RPC), so the per-pair work that depends on a wave's
+// columns (products, learning, outputs) is split four ways, and the wave
+// that learns most in a pair, which every workgroup waits for at the next
+// exchange, has at most CPW columns to redo.
+//   * Each wave gathers its own input words for the next pair at the start
+//     of a pair, into registers; they arrive during the exchange.
+//   * Wave 0 (the poller) reads the exchange and hands it to the other waves
+//     through LDS (two buffers by pair parity; `seen` counts the pairs
+//     handed over), so the exchange has one reader per workgroup.
+//   * The workgroup's entries are staged in LDS and, after a barrier, waves
+//     1..3 publish one array each as whole 64-bit words.
+//   * Only wave 0 decides to abort (kSeenAbort in `seen`), so every wave
+//     leaves the loop at the same point and no barrier is left waiting.
+// The pair loop is instantiated once for the poller and once for the other
+// waves, so that neither copy's memory waits are widened by the other's
+// accesses.
+template <bool B>
+struct PollRole {
+  static constexpr bool value = B;
+};
+
+template <int RPC, int NV, int RW>
+__global__ __launch_bounds__(kPersistWaves * kWave) void k_sp_persistent_w(PersistArgs a) {
+  constexpr uint32_t CPW = RW / RPC;
+  constexpr uint32_t CPAD = NV * 4 * kWave;        // entries per exchange array
+  constexpr uint32_t NARR = 3;                     // frame t, frame t+1 if lost, if won
+  constexpr uint32_t WGC = kPersistWaves * CPW;    // columns per workgroup
+  constexpr uint32_t kSeenAbort = 0xFFFFFFFFu;
+  static_assert(kPersistWaves == NARR + 1, "waves 1..3 publish the three arrays");
+  __shared__ uint64_t xl[2][NARR][NV][kWave];
+  __shared__ uint32_t pub[NARR][WGC];
+  __shared__ uint32_t seen;
+  const Shape sh = a.sh;
+  const uint32_t lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  const uint32_t gw = blockIdx.x * kPersistWaves + wave;
+  const uint32_t c_begin = gw * CPW;
+  const uint32_t wg_begin = blockIdx.x * WGC;
+  const uint32_t ncols = c_begin < sh.C ? min(CPW, sh.C - c_begin) : 0u;
+  if (threadIdx.x == 0) seen = 0;
+
+  // State: idx << 9 | q, and the mask of the input bit while connected;
+  // wi: the frame word each row reads (word 0 for rows without a synapse).
+  uint32_t st[RW], msk[RW], wi[RW];
+  uint32_t row_ok = 0;
+#pragma unroll
+  for (uint32_t r = 0; r < RW; ++r) {
+    const uint32_t j = r / RPC, s = (r % RPC) * kWave + lane;
+    const bool ok = j < ncols && s < sh.S;
+    const size_t off = ok ? (size_t)(c_begin + j) * sh.S + s : 0;
+    const uint32_t i = min(a.idx[off], sh.N - 1);
+    const uint32_t q = perm_to_q(a.perm[off]);
+    st[r] = ok ? (i << 9) | q : 0u;
+    msk[r] = (ok && q >= sh.theta) ? (1u << (i & 31u)) : 0u;
+    wi[r] = ok ? i >> 5 : 0u;
+    row_ok |= ok ? 1u << r : 0u;
+  }
+
+  uint64_t* x64w = reinterpret_cast<uint64_t*>(a.xchg);
+  const uint32_t rep = xcc_id() % a.replicas;
+  const bool mine = lane < ncols;
+  uint64_t ev0[NV], ev1[NV];
+#pragma unroll
+  for (int u = 0; u < NV; ++u) {
+    ev0[u] = 0;
+    ev1[u] = 0;
+  }
+  uint32_t guess = 1 + sh.S / 16;
+  FrameResult r0 = {0, 0, 0, 0, false}, r1 = {0, 0, 0, 0, false};
+  bool abort = false;
+  uint32_t prev_t = 0;
+  bool prev_two = false;
+
+  // This wave's entries of the three arrays, into the workgroup's staging.
+  auto stage = [&](const uint32_t(&o0)[CPW], const uint32_t(&oL)[CPW], const uint32_t(&oW)[CPW]) {
+    if (lane < CPW) {
+      pub[0][wave * CPW + lane] = lane_value(o0, lane);
+      pub[1][wave * CPW + lane] = lane_value(oL, lane);
+      pub[2][wave * CPW + lane] = lane_value(oW, lane);
+    }
+  };
+
+  // Input words of frames t and t + 1, each clamped to the last frame (a
+  // gather past the end is never used; issuing it unconditionally keeps the
+  // loads free of copies that would wait for them).
+  auto gather = [&](uint32_t t, uint32_t (&x0)[RW], uint32_t (&x1)[RW]) {
+    const uint32_t* f0 = a.frames + (size_t)min(t, a.F - 1) * sh.W;
+    const uint32_t* f1 = a.frames + (size_t)min(t + 1, a.F - 1) * sh.W;
+#pragma unroll
+    for (uint32_t r = 0; r < RW; ++r) {
+      x0[r] = f0[wi[r]];
+      x1[r] = f1[wi[r]];
+    }
+  };
+
+  // What a pair publishes, for the columns in `cols`: frame t's overlap, the
+  // state after learning frame t, and frame t + 1's overlap if the column
+  // loses frame t (same state) and if it wins it.
+  auto products = [&](uint32_t cols, const uint32_t (&x0)[RW], const uint32_t (&x1)[RW],
+                      uint32_t (&o0)[CPW], uint32_t (&oL)[CPW], uint32_t (&oW)[CPW],
+                      uint32_t (&sW)[RW], uint32_t (&mW)[RW]) {
+#pragma unroll
+    for (uint32_t j = 0; j < CPW; ++j) {
+      if ((cols >> j) & 1u) {
+        uint32_t c0 = 0, cL = 0, cW = 0;
+#pragma unroll
+        for (uint32_t rr = 0; rr < RPC; ++rr) {
+          const uint32_t r = j * RPC + rr;
+          const uint32_t i = st[r] >> 9;
+          const uint32_t q = learn_q(st[r] & 511u, input_bit(x0[r], i), sh);
+          const bool ok = a.learn && ((row_ok >> r) & 1u);
+          sW[r] = ok ? (i << 9) | q : st[r];
+          mW[r] = ok ? (q >= sh.theta ? 1u << (i & 31u) : 0u) : msk[r];
+          c0 += (uint32_t)__popcll(__ballot((x0[r] & msk[r]) != 0u));
+          cL += (uint32_t)__popcll(__ballot((x1[r] & msk[r]) != 0u));
+          cW += (uint32_t)__popcll(__ballot((x1[r] & mW[r]) != 0u));
+        }
+        const bool live = j < ncols;
+        o0[j] = (live && c0 >= sh.m) ? c0 : 0u;
+        oL[j] = (live && cL >= sh.m) ? cL : 0u;
+        oW[j] = (live && cW >= sh.m) ? cW : 0u;
+      }
+    }
+  };
+
+  constexpr uint32_t kAllCols = (1u << CPW) - 1u;
+  auto run = [&](auto role) {
+    constexpr bool POLL = decltype(role)::value;
+    uint32_t w0[RW], w1[RW];  // this pair's input words
+    uint32_t ov0[CPW], ovL[CPW], ovW[CPW];
+    uint32_t stW[RW], mskW[RW];
+    gather(0, w0, w1);
+    products(kAllCols, w0, w1, ov0, ovL, ovW, stW, mskW);
+    stage(ov0, ovL, ovW);
+    __syncthreads();
+    for (uint32_t t = 0; t < a.F; t += 2) {
+      const bool two = t + 1 < a.F;
+      const uint32_t pair = t / 2;
+      const uint32_t g = a.frame_base + pair;
+      const uint32_t slot = g & 1u;
+      const uint32_t tg = ((g + 1u) & 3u) << kTagShift;
+      const uint64_t* xs = x64w + (size_t)(rep * 2 + slot) * NARR * (CPAD / 4);
+
+      // Wave 1 + q publishes array q of the workgroup as whole 64-bit words
+      // (entries past C land in the padding that readers skip).
+      if constexpr (!POLL) {
+        const uint32_t arr = wave - 1;
+        if (lane < WGC / 4) {
+          const uint64_t word = (uint64_t)(tg | pub[arr][4 * lane]) |
+                                ((uint64_t)(tg | pub[arr][4 * lane + 1]) << 16) |
+                                ((uint64_t)(tg | pub[arr][4 * lane + 2]) << 32) |
+                                ((uint64_t)(tg | pub[arr][4 * lane + 3]) << 48);
+          for (uint32_t rr = 0; rr < a.replicas; ++rr)
+            store_word(x64w + (((size_t)(rr * 2 + slot) * NARR + arr) * CPAD + wg_begin) / 4 + lane,
+                       word);
+        }
+      }
+      // The next pair's input words, which arrive while the exchange is in flight.
+      const uint32_t tn = t + 2;
+      const bool has_next = tn < a.F;
+      uint32_t n0[RW], n1[RW];
+      gather(tn, n0, n1);
+      uint64_t v0[NV], vL[NV], vW[NV];
+      if (t > 0) {
+        write_frame(a, ev0, r0, prev_t, lane, mine, c_begin, gw == 0);
+        if (prev_two) write_frame(a, ev1, r1, prev_t + 1, lane, mine, c_begin, gw == 0);
+      }
+
+      // The next pair's products with the current state, while the exchange
+      // is in flight; redone below for the columns that learn in this pair.
+      uint32_t sov0[CPW], sovL[CPW], sovW[CPW];
+      uint32_t sstW[RW], smskW[RW];
+      if (has_next) products(kAllCols, n0, n1, sov0, sovL, sovW, sstW, smskW);
+
+      if constexpr (POLL) {
+        // First read of the exchange after the outputs and the speculation
+        // (a read that comes back stale costs a whole further round trip).
+#pragma unroll
+        for (int u = 0; u < NV; ++u) {
+          v0[u] = load_entries(xs + u * kWave + lane);
+          vL[u] = load_entries(xs + CPAD / 4 + u * kWave + lane);
+          vW[u] = load_entries(xs + 2 * (CPAD / 4) + u * kWave + lane);
+        }
+        const uint64_t tagw = (uint64_t)tg * kOnes16;
+        uint32_t spins = 0;
+        while (true) {
+          bool ok = true;
+#pragma unroll
+          for (int u = 0; u < NV; ++u) {
+            const uint64_t tm = tag_mask(u, lane, sh.C);
+            ok = ok && ((v0[u] ^ tagw) & tm) == 0ull && ((vL[u] ^ tagw) & tm) == 0ull &&
+                 ((vW[u] ^ tagw) & tm) == 0ull;
+          }
+          if (__all(ok)) break;
+          if (++spins > a.spin_limit || ((spins & 63u) == 0 && load_tagged(a.err) != 0)) {
+            abort = true;
+            break;
+          }
+#pragma unroll
+          for (int u = 0; u < NV; ++u) {
+            const uint64_t tm = tag_mask(u, lane, sh.C);
+            if (((v0[u] ^ tagw) & tm) != 0ull) v0[u] = load_entries(xs + u * kWave + lane);
+            if (((vL[u] ^ tagw) & tm) != 0ull) vL[u] = load_entries(xs + CPAD / 4 + u * kWave + lane);
+            if (((vW[u] ^ tagw) & tm) != 0ull)
+              vW[u] = load_entries(xs + 2 * (CPAD / 4) + u * kWave + lane);
+          }
+        }
+        if (abort) {
+          lds_release(&seen, kSeenAbort);
+          break;
+        }
+#pragma unroll
+        for (int u = 0; u < NV; ++u) {
+          xl[pair & 1][0][u][lane] = v0[u];
+          xl[pair & 1][1][u][lane] = vL[u];
+          xl[pair & 1][2][u][lane] = vW[u];
+        }
+        lds_release(&seen, pair + 1);
+      } else {
+        // Bounded by wave 0, which sets `seen` within its own spin limit.
+        uint32_t sv;
+        while ((sv = lds_acquire(&seen)) <= pair) __builtin_amdgcn_s_sleep(0);
+        if (sv == kSeenAbort) {
+          abort = true;
+          break;
+        }
+#pragma unroll
+        for (int u = 0; u < NV; ++u) {
+          v0[u] = xl[pair & 1][0][u][lane];
+          vL[u] = xl[pair & 1][1][u][lane];
+          vW[u] = xl[pair & 1][2][u][lane];
+        }
+      }
+
+      // Frame t: threshold, and which own columns win.
+      const uint32_t my0 = lane_value(ov0, lane);
+#pragma unroll
+      for (int u = 0; u < NV; ++u) ev0[u] = v0[u] & kFieldBits;
+      uint32_t c_hi;
+      const uint32_t T0 = topk_threshold(ev0, sh.S, sh.k, guess, &c_hi);
+      r0.T = T0;
+      r0.need = T0 ? sh.k - c_hi : 0u;
+      r0.nsel = T0 ? sh.k : c_hi;
+      r0.ov = my0;
+      r0.sel = own_wins(ev0, my0, mine, T0, r0.need, lane, c_begin);
+      if (T0) guess = T0;
+
+      // Frame t + 1: every column's overlap given frame t's winners.
+      if (two) {
+        uint64_t fm[NV];
+        select_all(ev0, T0, r0.need, lane, fm);
+#pragma unroll
+        for (int u = 0; u < NV; ++u)
+          ev1[u] = ((vL[u] & ~fm[u]) | (vW[u] & fm[u])) & kFieldBits;
+        const uint32_t my1 = r0.sel ? lane_value(ovW, lane) : lane_value(ovL, lane);
+        const uint32_t T1 = topk_threshold(ev1, sh.S, sh.k, guess, &c_hi);
+        r1.T = T1;
+        r1.need = T1 ? sh.k - c_hi : 0u;
+        r1.nsel = T1 ? sh.k : c_hi;
+        r1.ov = my1;
+        r1.sel = own_wins(ev1, my1, mine, T1, r1.need, lane, c_begin);
+        if (T1) guess = T1;
+      }
+
+      // Learning on the own columns that won (frame t's state, then frame t+1).
+      uint32_t changed = 0;
+      if (a.learn) {
+        const uint32_t sel0 = (uint32_t)__ballot(r0.sel) & kAllCols;
+        const uint32_t sel1 = two ? (uint32_t)__ballot(r1.sel) & kAllCols : 0u;
+        changed = sel0 | sel1;
+#pragma unroll
+        for (uint32_t j = 0; j < CPW; ++j) {
+          if ((changed >> j) & 1u) {
+#pragma unroll
+            for (uint32_t rr = 0; rr < RPC; ++rr) {
+              const uint32_t r = j * RPC + rr;
+              if ((sel0 >> j) & 1u) {
+                st[r] = stW[r];
+                msk[r] = mskW[r];
+              }
+              if ((sel1 >> j) & 1u) {
+                const uint32_t i = st[r] >> 9;
+                const uint32_t q = learn_q(st[r] & 511u, input_bit(w1[r], i), sh);
+                const bool ok = (row_ok >> r) & 1u;
+                st[r] = ok ? (i << 9) | q : st[r];
+                msk[r] = ok ? (q >= sh.theta ? 1u << (i & 31u) : 0u) : msk[r];
+              }
+            }
+          }
+        }
+      }
+      prev_t = t;
+      prev_two = two;
+
+      if (has_next) {
+        if (changed) products(changed, n0, n1, sov0, sovL, sovW, sstW, smskW);
+#pragma unroll
+        for (uint32_t r = 0; r < RW; ++r) {
+          w0[r] = n0[r];
+          w1[r] = n1[r];
+          stW[r] = sstW[r];
+          mskW[r] = smskW[r];
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < CPW; ++j) {
+          ov0[j] = sov0[j];
+          ovL[j] = sovL[j];
+          ovW[j] = sovW[j];
+        }
+        stage(ov0, ovL, ovW);
+      }
+      __syncthreads();
+    }
+  };
+  if (a.F > 0) {
+    if (wave == 0)
+      run(PollRole<true>{});
+    else
+      run(PollRole<false>{});
+  }
+
+  if (abort) {
+    if (wave == 0 && lane == 0) store_tagged(a.err, 1u);
+    return;
+  }
+  if (a.F > 0) {
+    write_frame(a, ev0, r0, prev_t, lane, mine, c_begin, gw == 0);
+    if (prev_two) write_frame(a, ev1, r1, prev_t + 1, lane, mine, c_begin, gw == 0);
+  }
+  if (a.learn) {
+#pragma unroll
+    for (uint32_t r = 0; r < RW; ++r) {
       const uint32_t j = r / RPC, s = (r % RPC) * kWave + lane;
       if ((row_ok >> r) & 1u) a.perm[(size_t)(c_begin + j) * sh.S + s] = q_to_perm(st[r] & 511u);
     }
@@ -666,6 +1012,21 @@ const void* persistent_kernel(uint32_t rpc, uint32_t nv, uint32_t rows) {
   HTMSP_PK_V(1, 16) HTMSP_PK_V(2, 16) HTMSP_PK_V(4, 16) HTMSP_PK_V(8, 16) HTMSP_PK_V(16, 16)
 #undef HTMSP_PK_V
 #undef HTMSP_PK
+  return nullptr;
+}
+
+const void* persistent_wave_kernel(uint32_t rpc, uint32_t nv, uint32_t rw) {
+#define HTMSP_PW(P, V, R)                              \
+  if (rpc == P && nv == V && rw == R)                  \
+    return reinterpret_cast<const void*>(&k_sp_persistent_w<P, V, R>);
+  // The shapes a 256-CU device reaches with one workgroup per CU: C <= 256 *
+  // 4 * rw / rpc columns, nv covering C.
+  HTMSP_PW(1, 1, 4) HTMSP_PW(1, 2, 4) HTMSP_PW(1, 4, 4) HTMSP_PW(1, 8, 4) HTMSP_PW(1, 16, 4)
+  HTMSP_PW(2, 1, 4) HTMSP_PW(2, 2, 4) HTMSP_PW(2, 4, 4) HTMSP_PW(2, 8, 4) HTMSP_PW(2, 16, 8)
+  HTMSP_PW(4, 1, 4) HTMSP_PW(4, 2, 4) HTMSP_PW(4, 4, 4) HTMSP_PW(4, 8, 8) HTMSP_PW(4, 16, 16)
+  HTMSP_PW(8, 1, 8) HTMSP_PW(8, 2, 8) HTMSP_PW(8, 4, 8) HTMSP_PW(8, 8, 16)
+  HTMSP_PW(16, 1, 16) HTMSP_PW(16, 2, 16) HTMSP_PW(16, 4, 16)
+#undef HTMSP_PW
   return nullptr;
 }
 

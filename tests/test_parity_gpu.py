@@ -108,6 +108,29 @@ def test_paper_scale_sweep_points(C, S):
     check(synth.workload_paper_scale(frames=40, columns=C, synapses=S), expect_persistent=True)
 
 
+# One shape per instance of the one-column-group-per-wave persistent kernel
+# (rows per column, exchange words per lane, rows per wave), each picked so
+# that the planner lands on it: (C, S) with 7 frames (an odd count, so the
+# last exchange carries one frame).
+WAVE_SHAPES = [
+    (64, 40), (300, 64), (1000, 50), (2000, 33), (4096, 64),          # 1 row per column
+    (200, 100), (500, 128), (1024, 65), (2048, 128), (3000, 100),     # 2
+    (256, 256), (400, 200), (1000, 256), (1500, 256), (4000, 200),    # 4
+    (100, 512), (512, 300), (1024, 512), (2048, 400),                 # 8
+    (200, 1000), (300, 1024), (1024, 700),                            # 16
+]
+
+
+@pytest.mark.parametrize("C,S", WAVE_SHAPES, ids=[f"C{c}_S{s}" for c, s in WAVE_SHAPES])
+def test_persistent_instances(C, S):
+    cfg = synth.sp_config(20000, C, S, 3, max(1, C // 25))
+    w = synth.random_instance(900 + C + S, cfg, frames=7, density=0.08)
+    check(w, expect_persistent=True)
+    pool = sp.SpatialPooler(w.cfg, w.idx, w.perm)
+    assert pool.kernel == "k_sp_persistent_w"
+    pool.close()
+
+
 def test_split_launches_equal_one_launch():
     w = synth.workload_paper_scale(frames=60, columns=512, synapses=128)
     check(w, chunks=[1, 2, 3, 10, 11, 40])

@@ -481,7 +481,8 @@ def bench_local(args, torch, sp, synth):
                    "frames_per_step": F, "active_per_frame": n_act / F, "path": "local"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_overlap_plain + k_inhibit_local + k_learn_active",
+                     "kernel": (pool.local_kernel if pool.local_kernel != "plain" else
+                                "k_overlap_plain + k_inhibit_local + k_learn_active"),
                      "kernel_ms_per_launch": call_ms, "algorithmic_bytes_per_launch": abytes,
                      "counter_bytes_per_launch": None},
         "cpu_baseline": cpu,

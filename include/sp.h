@@ -215,9 +215,12 @@ int sp_inhibit_local(const int32_t* overlaps_dev, uint32_t num_frames, uint32_t 
 
 /* Frames in order through overlap (Algorithm 1), local inhibition (as
  * sp_inhibit_local, n = the handle's `winners`) and, when learn != 0,
- * learning on the active columns; one launch sequence per frame.
- * overlaps_dev [F][C] may be NULL; active_dev is [F][C] uint8.  The
- * handle's histogram, if set, is not updated by this call. */
+ * learning on the active columns.  One persistent launch for all frames
+ * where the shape allows it (C <= 4096, S <= 1024, see
+ * sp_step_local_kernel), else one launch sequence per frame; the results
+ * are the same.  overlaps_dev [F][C] may be NULL; active_dev is [F][C]
+ * uint8.  The handle's histogram, if set, is not updated by this call.  A
+ * device-side failure of the persistent launch is reported by sp_sync. */
 int sp_step_local(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames, int learn,
                   uint32_t grid_w, uint32_t radius, int32_t* overlaps_dev, uint8_t* active_dev,
                   void* stream);
@@ -276,6 +279,11 @@ int sp_step_is_persistent(const sp_handle* h);
 #define SP_KERNEL_PERSISTENT_GROUP 1
 #define SP_KERNEL_PERSISTENT_WAVE 2
 int sp_step_kernel(const sp_handle* h);
+
+/* Which execution sp_step_local uses for this handle's shape on its device:
+ * SP_KERNEL_PLAIN (three launches a frame) or SP_KERNEL_PERSISTENT_WAVE (one
+ * persistent launch, a column group per wave); negative on a bad handle. */
+int sp_step_local_kernel(const sp_handle* h);
 
 /* Synchronises `stream` and reports a device-side failure of an earlier
  * step on this handle (SP_EDEVICE, after which the handle is SP_EBROKEN). */

@@ -42,6 +42,12 @@ struct sp_handle {
   const void* pkernel;
   size_t plds;
   int pkind;  // SP_KERNEL_* of the persistent instance
+  // persistent local-inhibition step: instance (null: per-frame launches),
+  // grid, its exchange and the count of exchanges it has used
+  const void* lkernel;
+  uint32_t lgrid;
+  uint64_t* xloc;
+  uint64_t xloc_frames;
   bool broken;
   int cus;
   // Every learning step and every re-validation changes the state version;
@@ -83,7 +89,7 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Workspace layout, each part 256-byte aligned.
 struct WsLayout {
-  size_t xchg, err, check, ov, many_ovx, many_dec, total;
+  size_t xchg, err, check, ov, many_ovx, many_dec, xloc, total;
 };
 
 WsLayout ws_layout(const sp_config& c) {
@@ -98,7 +104,8 @@ WsLayout ws_layout(const sp_config& c) {
   l.many_ovx = align_up(l.ov + sizeof(int32_t) * (size_t)c.num_columns, 256);
   // read in pairs of entries by 256-column words
   l.many_dec = align_up(l.many_ovx + sizeof(uint32_t) * align_up(c.num_columns, 256), 256);
-  l.total = align_up(l.many_dec + sizeof(uint64_t), 256);
+  l.xloc = align_up(l.many_dec + sizeof(uint64_t), 256);
+  l.total = align_up(l.xloc + htmsp::persistent_local_exchange_bytes(c.num_columns), 256);
   return l;
 }
 
@@ -192,6 +199,7 @@ uint32_t next_pow2(uint32_t x) {
 // else the 16-rows-per-workgroup kernel; the grid must be co-resident.
 void plan_persistent(sp_handle* h) {
   h->persistent = false;
+  h->lkernel = nullptr;
   int dev = h->device, cus = 0, coop = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return;
   if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess) return;
@@ -201,6 +209,21 @@ void plan_persistent(sp_handle* h) {
     return;
   const uint32_t rpc = next_pow2((sh.S + 63) / 64);
   const uint32_t nv = next_pow2(htmsp::persistent_exchange_entries(sh.C) / 256);
+  // The local-inhibition step: the same column split, one workgroup per CU.
+  for (uint32_t rw = std::max(4u, rpc); rw <= 16; rw *= 2) {
+    const uint32_t cols = rw / rpc * htmsp::kPersistWaves;
+    const uint32_t grid = (sh.C + cols - 1) / cols;
+    if (grid > (uint32_t)cus) continue;
+    const void* kl = htmsp::persistent_local_kernel(rpc, nv, rw);
+    int per_cu = 0;
+    if (kl && hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kl, htmsp::kPersistWaves * 64,
+                                                           0) == hipSuccess &&
+        per_cu >= 1) {
+      h->lkernel = kl;
+      h->lgrid = grid;
+    }
+    break;
+  }
   // One column group per wave, one workgroup per CU: the fewest rows per
   // wave (4, 8 or 16, at least one column) that keep the grid to one
   // workgroup per CU.
@@ -456,6 +479,7 @@ int sp_create(const sp_config* cfg, uint32_t* idx_dev, float* perm_dev, void* st
   h->ov_scratch = reinterpret_cast<int32_t*>(base + l.ov);
   h->many_ovx = reinterpret_cast<uint32_t*>(base + l.many_ovx);
   h->many_dec = reinterpret_cast<uint64_t*>(base + l.many_dec);
+  h->xloc = reinterpret_cast<uint64_t*>(base + l.xloc);
   e = hipMemsetAsync(h->ws, 0, l.total, s);
   if (e != hipSuccess) {
     (void)hipFree(h->ws);
@@ -743,6 +767,30 @@ int sp_step_local(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames,
   DeviceScope ds(h->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (learn) ++h->state_version;
+  if (h->lkernel) {
+    htmsp::LocalArgs a;
+    a.idx = h->idx;
+    a.perm = h->perm;
+    a.frames = frames_dev;
+    a.ov_out = overlaps_dev;
+    a.active_out = active_dev;
+    a.xchg = h->xloc;
+    a.err = h->err;
+    a.F = num_frames;
+    a.learn = learn ? 1u : 0u;
+    a.frame_base = (uint32_t)h->xloc_frames;
+    a.replicas = htmsp::kPersistReplicas;
+    a.spin_limit = kSpinLimit;
+    a.grid_w = grid_w;
+    a.radius = radius;
+    a.sh = sh;
+    void* args[] = {&a};
+    hipError_t e = hipLaunchCooperativeKernel(h->lkernel, dim3(h->lgrid),
+                                              dim3(htmsp::kPersistWaves * 64), args, 0, s);
+    if (e != hipSuccess) return hip_fail(e, "persistent local step launch");
+    h->xloc_frames += num_frames;
+    return ok();
+  }
   for (uint32_t t = 0; t < num_frames; ++t) {
     const uint32_t* frame = frames_dev + (size_t)t * sh.W;
     int32_t* ov = overlaps_dev ? overlaps_dev + (size_t)t * sh.C : h->ov_scratch;
@@ -893,6 +941,11 @@ int sp_set_histogram(sp_handle* h, uint32_t* hist_dev) {
 int sp_step_is_persistent(const sp_handle* h) {
   if (!h) return fail(SP_EINVAL, "handle is NULL");
   return h->persistent ? 1 : 0;
+}
+
+int sp_step_local_kernel(const sp_handle* h) {
+  if (!h) return fail(SP_EINVAL, "handle is NULL");
+  return h->lkernel ? SP_KERNEL_PERSISTENT_WAVE : SP_KERNEL_PLAIN;
 }
 
 int sp_step_kernel(const sp_handle* h) {

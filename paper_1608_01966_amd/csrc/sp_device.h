@@ -193,5 +193,45 @@ __device__ __forceinline__ uint32_t topk_threshold(const uint64_t (&ev)[NV], uin
   return lo;
 }
 
+// ---- Persistent exchanges between workgroups ----
+__device__ __forceinline__ void lds_release(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Agent-scope 64-bit store and load of four packed exchange entries.
+__device__ __forceinline__ void store_word(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint64_t load_entries(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Element `lane` of a wave-uniform array, in lane `lane` (0 past CPW).
+template <int CPW>
+__device__ __forceinline__ uint32_t lane_value(const uint32_t (&ovs)[CPW], uint32_t lane) {
+  uint32_t v = 0;
+#pragma unroll
+  for (uint32_t j = 0; j < (uint32_t)CPW; ++j) v = lane == j ? ovs[j] : v;
+  return v;
+}
+
+// The XCD this wave runs on.
+__device__ __forceinline__ uint32_t xcc_id() {
+  uint32_t v;
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(v));
+  return v;
+}
+
+// Tag bits to check in exchange word u of this lane, whose entries are
+// columns u * 256 + 4 * lane + {0..3} (entries at or past C are never
+// written and are skipped).
+__device__ __forceinline__ uint64_t tag_mask(uint32_t u, uint32_t lane, uint32_t C) {
+  const uint32_t cb = u * 4 * kWave + 4 * lane;
+  if (cb + 4 <= C) return kTagBits;
+  const uint32_t n = C > cb ? C - cb : 0u;
+  return ((1ull << (16 * n)) - 1ull) & kTagBits;
+}
+
 }  // namespace dev
 }  // namespace htmsp

@@ -58,6 +58,27 @@ uint32_t persistent_exchange_entries(uint32_t C);
 // 64-bit exchange words per lane (1, 2, 4, 8 or 16) and `rows` rows per
 // workgroup (kPersistRows); nullptr otherwise.
 const void* persistent_kernel(uint32_t rpc, uint32_t nv, uint32_t rows);
+// Persistent learning step with local inhibition: F frames in one
+// cooperative launch, one frame per exchange of every column's overlap.
+struct LocalArgs {
+  const uint32_t* idx;
+  float* perm;
+  const uint32_t* frames;
+  int32_t* ov_out;     // [F][C] or null
+  uint8_t* active_out; // [F][C]
+  uint64_t* xchg;      // [replicas][2][entries / 4] tagged overlaps
+  uint32_t* err;
+  uint32_t F, learn, frame_base, replicas, spin_limit;
+  uint32_t grid_w, radius;  // the neighbourhood; n = sh.k
+  Shape sh;
+};
+// The persistent local-inhibition instance for `rpc` rows per column, `nv`
+// exchange words per lane and `rw` rows per wave (kPersistWaves waves per
+// workgroup, one workgroup per CU); nullptr otherwise.
+const void* persistent_local_kernel(uint32_t rpc, uint32_t nv, uint32_t rw);
+// Exchange bytes of the persistent local step for C columns.
+size_t persistent_local_exchange_bytes(uint32_t C);
+
 // Waves per workgroup of the one-column-group-per-wave kernel.
 constexpr uint32_t kPersistWaves = 4;
 // The one-column-group-per-wave instance for `rpc` rows per column, `nv`

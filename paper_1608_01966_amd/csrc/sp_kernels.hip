@@ -191,10 +191,6 @@ __global__ __launch_bounds__(256) void k_learn_plain(const uint32_t* __restrict_
 // rewritten only after every workgroup has finished reading it.
 constexpr uint32_t kRing = 8;
 
-__device__ __forceinline__ void lds_release(uint32_t* p, uint32_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-
 __device__ __forceinline__ void store_entry(uint16_t* p, uint16_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -203,52 +199,6 @@ __device__ __forceinline__ void store_half(uint32_t* p, uint32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ void store_word(uint64_t* p, uint64_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ uint64_t load_entries(const uint64_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ uint32_t xcc_id() {
-  uint32_t v;
-  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(v));
-  return v;
-}
-
-// Tag bits to check in exchange word u of this lane (entries at or past C
-// are never written and are skipped).
-__device__ __forceinline__ uint64_t tag_mask(uint32_t u, uint32_t lane, uint32_t C) {
-  const uint32_t cb = u * 4 * kWave + 4 * lane;
-  if (cb + 4 <= C) return kTagBits;
-  const uint32_t n = C > cb ? C - cb : 0u;
-  return ((1ull << (16 * n)) - 1ull) & kTagBits;
-}
-
-// Own columns: overlaps of this group's columns for one frame (Algorithm 1,
-// gated at min_overlap), as wave-uniform values.
-template <int RPC, int CPW, int ROWS>
-__device__ __forceinline__ void group_overlaps(const uint32_t (&w)[ROWS],
-                                               const uint32_t (&msk)[ROWS], uint32_t ncols,
-                                               uint32_t m, uint32_t (&ovs)[CPW]) {
-#pragma unroll
-  for (uint32_t j = 0; j < (uint32_t)CPW; ++j) {
-    uint32_t raw = 0;
-#pragma unroll
-    for (uint32_t rr = 0; rr < (uint32_t)RPC; ++rr)
-      raw += (uint32_t)__popcll(__ballot((w[j * RPC + rr] & msk[j * RPC + rr]) != 0u));
-    ovs[j] = (j < ncols && raw >= m) ? raw : 0u;
-  }
-}
-
-template <int CPW>
-__device__ __forceinline__ uint32_t lane_value(const uint32_t (&ovs)[CPW], uint32_t lane) {
-  uint32_t v = 0;
-#pragma unroll
-  for (uint32_t j = 0; j < (uint32_t)CPW; ++j) v = lane == j ? ovs[j] : v;
-  return v;
-}
 
 // Whether this lane's own column (overlap v, lane < ncols) wins: above T, or
 // equal to T and among the first `need` such columns in column order.

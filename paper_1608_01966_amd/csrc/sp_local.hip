@@ -79,6 +79,214 @@ __global__ __launch_bounds__(256) void k_learn_active(const uint32_t* __restrict
   }
 }
 
+// Persistent learning step with local inhibition: F frames in one
+// cooperative launch.  Columns are split as in the global persistent kernel
+// (kPersistWaves waves per workgroup, a group of CPW = RW / RPC consecutive
+// columns per wave, synapse state in registers for the whole launch).  Per
+// frame every wave publishes its columns' overlaps through a tagged exchange
+// (one 16-bit entry [tag:2 | overlap:14] per column; frame g of the handle's
+// local sequence uses slot g & 1 and tag (g + 1) & 3), wave 0 of each
+// workgroup reads every column's entry into LDS, and each wave then decides
+// its own columns by scanning their neighbourhoods in LDS, learns on the
+// active ones and computes its next overlaps (speculatively before the
+// exchange wait, redone for the columns that learned).  Only wave 0 decides
+// to abort, through the LDS pair counter, so no barrier is left waiting.
+template <bool B>
+struct LocalRole {
+  static constexpr bool value = B;
+};
+
+template <int RPC, int NV, int RW>
+__global__ __launch_bounds__(kPersistWaves * kWave) void k_sp_persistent_local(LocalArgs a) {
+  constexpr uint32_t CPW = RW / RPC;
+  constexpr uint32_t WGC = kPersistWaves * CPW;  // columns per workgroup
+  constexpr uint32_t kSeenAbort = 0xFFFFFFFFu;
+  // Every column's overlap of one frame (two buffers by frame parity): the
+  // exchange words hold columns u * 256 + 4 * lane + q, so word u * 64 + lane
+  // of the copy is columns 4 * (u * 64 + lane) + q and the copy indexes by
+  // column as 16-bit entries.
+  __shared__ uint64_t xl[2][NV * kWave];
+  __shared__ uint32_t pub[WGC];
+  __shared__ uint32_t seen;
+  const Shape sh = a.sh;
+  const uint32_t lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  const uint32_t gw = blockIdx.x * kPersistWaves + wave;
+  const uint32_t c_begin = gw * CPW;
+  const uint32_t wg_begin = blockIdx.x * WGC;
+  const uint32_t ncols = c_begin < sh.C ? min(CPW, sh.C - c_begin) : 0u;
+  const uint32_t rows = (sh.C + a.grid_w - 1) / a.grid_w;
+  if (threadIdx.x == 0) seen = 0;
+
+  uint32_t st[RW], msk[RW], wi[RW];
+  uint32_t row_ok = 0;
+#pragma unroll
+  for (uint32_t r = 0; r < RW; ++r) {
+    const uint32_t j = r / RPC, s = (r % RPC) * kWave + lane;
+    const bool ok = j < ncols && s < sh.S;
+    const size_t off = ok ? (size_t)(c_begin + j) * sh.S + s : 0;
+    const uint32_t i = min(a.idx[off], sh.N - 1);
+    const uint32_t q = perm_to_q(a.perm[off]);
+    st[r] = ok ? (i << 9) | q : 0u;
+    msk[r] = (ok && q >= sh.theta) ? (1u << (i & 31u)) : 0u;
+    wi[r] = ok ? i >> 5 : 0u;
+    row_ok |= ok ? 1u << r : 0u;
+  }
+  const uint32_t rep = xcc_id() % a.replicas;
+  bool abort = false;
+
+  // Input words of frame t (clamped to the last frame: unconditional loads).
+  auto gather = [&](uint32_t t, uint32_t (&x)[RW]) {
+    const uint32_t* f = a.frames + (size_t)min(t, a.F - 1) * sh.W;
+#pragma unroll
+    for (uint32_t r = 0; r < RW; ++r) x[r] = f[wi[r]];
+  };
+  // Gated overlaps (Algorithm 1) of the columns in `cols` with the current state.
+  auto overlaps = [&](uint32_t cols, const uint32_t (&x)[RW], uint32_t (&o)[CPW]) {
+#pragma unroll
+    for (uint32_t j = 0; j < CPW; ++j) {
+      if ((cols >> j) & 1u) {
+        uint32_t c = 0;
+#pragma unroll
+        for (uint32_t rr = 0; rr < RPC; ++rr) {
+          const uint32_t r = j * RPC + rr;
+          c += (uint32_t)__popcll(__ballot((x[r] & msk[r]) != 0u));
+        }
+        o[j] = (j < ncols && c >= sh.m) ? c : 0u;
+      }
+    }
+  };
+  // Algorithm 2 for column c with overlap v against the frame's copy: active
+  // iff v >= 2 and fewer than n other columns of its neighbourhood have an
+  // overlap >= v (lanes split each row of the window; stops at n).
+  auto decide = [&](uint32_t c, uint32_t v, const uint16_t* ov) {
+    if (v < 2) return false;
+    const uint32_t cx = c % a.grid_w, cy = c / a.grid_w;
+    const uint32_t y0 = cy >= a.radius ? cy - a.radius : 0u;
+    const uint32_t y1 = min(cy + a.radius, rows - 1);
+    const uint32_t x0 = cx >= a.radius ? cx - a.radius : 0u;
+    const uint32_t x1 = min(cx + a.radius, a.grid_w - 1);
+    uint32_t k = 0;
+    for (uint32_t y = y0; y <= y1 && k < sh.k; ++y) {
+      for (uint32_t xb = x0; xb <= x1 && k < sh.k; xb += kWave) {
+        const uint32_t x = xb + lane, d = y * a.grid_w + x;
+        const bool hit = x <= x1 && d < sh.C && d != c && (ov[d] & 0x3FFFu) >= v;
+        k += (uint32_t)__popcll(__ballot(hit));
+      }
+    }
+    return k < sh.k;
+  };
+
+  auto run = [&](auto role) {
+    constexpr bool POLL = decltype(role)::value;
+    uint32_t w[RW], o[CPW];
+    gather(0, w);
+    overlaps((1u << CPW) - 1u, w, o);
+    if (lane < CPW) pub[wave * CPW + lane] = lane_value(o, lane);
+    __syncthreads();
+    for (uint32_t t = 0; t < a.F; ++t) {
+      const uint32_t g = a.frame_base + t;
+      const uint32_t slot = g & 1u;
+      const uint32_t tg = ((g + 1u) & 3u) << kTagShift;
+      uint64_t* xs = a.xchg + (size_t)(rep * 2 + slot) * NV * kWave;
+      // Wave 1 publishes the workgroup's entries as whole 64-bit words.
+      if (!POLL && wave == 1 && lane < WGC / 4) {
+        const uint64_t word = (uint64_t)(tg | pub[4 * lane]) |
+                              ((uint64_t)(tg | pub[4 * lane + 1]) << 16) |
+                              ((uint64_t)(tg | pub[4 * lane + 2]) << 32) |
+                              ((uint64_t)(tg | pub[4 * lane + 3]) << 48);
+        for (uint32_t rr = 0; rr < a.replicas; ++rr)
+          store_word(a.xchg + (size_t)(rr * 2 + slot) * NV * kWave + wg_begin / 4 + lane, word);
+      }
+      uint32_t nx[RW], on[CPW];
+      gather(t + 1, nx);
+      overlaps((1u << CPW) - 1u, nx, on);  // speculation: no own column learns
+
+      if constexpr (POLL) {
+        uint64_t v[NV];
+#pragma unroll
+        for (int u = 0; u < NV; ++u) v[u] = load_entries(xs + u * kWave + lane);
+        const uint64_t tagw = (uint64_t)tg * kOnes16;
+        uint32_t spins = 0;
+        while (true) {
+          bool ok = true;
+#pragma unroll
+          for (int u = 0; u < NV; ++u) ok = ok && ((v[u] ^ tagw) & tag_mask(u, lane, sh.C)) == 0ull;
+          if (__all(ok)) break;
+          if (++spins > a.spin_limit || ((spins & 63u) == 0 && load_tagged(a.err) != 0)) {
+            abort = true;
+            break;
+          }
+#pragma unroll
+          for (int u = 0; u < NV; ++u)
+            if (((v[u] ^ tagw) & tag_mask(u, lane, sh.C)) != 0ull)
+              v[u] = load_entries(xs + u * kWave + lane);
+        }
+        if (abort) {
+          lds_release(&seen, kSeenAbort);
+          break;
+        }
+#pragma unroll
+        for (int u = 0; u < NV; ++u) xl[t & 1][u * kWave + lane] = v[u];
+        lds_release(&seen, t + 1);
+      } else {
+        // Bounded by wave 0, which sets `seen` within its own spin limit.
+        uint32_t sv;
+        while ((sv = lds_acquire(&seen)) <= t) __builtin_amdgcn_s_sleep(0);
+        if (sv == kSeenAbort) {
+          abort = true;
+          break;
+        }
+      }
+
+      // Own columns: decision, outputs, learning on the active ones.
+      const uint16_t* ov16 = reinterpret_cast<const uint16_t*>(xl[t & 1]);
+      uint32_t act = 0;
+#pragma unroll
+      for (uint32_t j = 0; j < CPW; ++j)
+        if (j < ncols && decide(c_begin + j, o[j], ov16)) act |= 1u << j;
+      if (lane < ncols) {
+        a.active_out[(size_t)t * sh.C + c_begin + lane] = (uint8_t)((act >> lane) & 1u);
+        if (a.ov_out) a.ov_out[(size_t)t * sh.C + c_begin + lane] = (int32_t)lane_value(o, lane);
+      }
+      if (a.learn && act) {
+#pragma unroll
+        for (uint32_t r = 0; r < RW; ++r) {
+          if ((act >> (r / RPC)) & (row_ok >> r) & 1u) {
+            const uint32_t i = st[r] >> 9;
+            const uint32_t q = learn_q(st[r] & 511u, input_bit(w[r], i), sh);
+            st[r] = (i << 9) | q;
+            msk[r] = q >= sh.theta ? 1u << (i & 31u) : 0u;
+          }
+        }
+        overlaps(act, nx, on);
+      }
+#pragma unroll
+      for (uint32_t r = 0; r < RW; ++r) w[r] = nx[r];
+#pragma unroll
+      for (uint32_t j = 0; j < CPW; ++j) o[j] = on[j];
+      if (lane < CPW) pub[wave * CPW + lane] = lane_value(o, lane);
+      __syncthreads();
+    }
+  };
+  if (a.F > 0) {
+    if (wave == 0)
+      run(LocalRole<true>{});
+    else
+      run(LocalRole<false>{});
+  }
+  if (abort) {
+    if (wave == 0 && lane == 0) store_tagged(a.err, 1u);
+    return;
+  }
+  if (a.learn) {
+#pragma unroll
+    for (uint32_t r = 0; r < RW; ++r) {
+      const uint32_t j = r / RPC, s = (r % RPC) * kWave + lane;
+      if ((row_ok >> r) & 1u) a.perm[(size_t)(c_begin + j) * sh.S + s] = q_to_perm(st[r] & 511u);
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t launch_inhibit_local(const int32_t* ov, uint32_t F, uint32_t C, uint32_t grid_w,
@@ -100,6 +308,24 @@ hipError_t launch_learn_active(const uint32_t* idx, float* perm, const uint32_t*
   hipLaunchKernelGGL(k_learn_active, dim3((sh.C + 3) / 4), dim3(256), 0, s, idx, perm, frame,
                      active, sh);
   return hipGetLastError();
+}
+
+const void* persistent_local_kernel(uint32_t rpc, uint32_t nv, uint32_t rw) {
+#define HTMSP_PL(P, V, R)                              \
+  if (rpc == P && nv == V && rw == R)                  \
+    return reinterpret_cast<const void*>(&k_sp_persistent_local<P, V, R>);
+  // The shapes a 256-CU device reaches with one workgroup per CU.
+  HTMSP_PL(1, 1, 4) HTMSP_PL(1, 2, 4) HTMSP_PL(1, 4, 4) HTMSP_PL(1, 8, 4) HTMSP_PL(1, 16, 4)
+  HTMSP_PL(2, 1, 4) HTMSP_PL(2, 2, 4) HTMSP_PL(2, 4, 4) HTMSP_PL(2, 8, 4) HTMSP_PL(2, 16, 8)
+  HTMSP_PL(4, 1, 4) HTMSP_PL(4, 2, 4) HTMSP_PL(4, 4, 4) HTMSP_PL(4, 8, 8) HTMSP_PL(4, 16, 16)
+  HTMSP_PL(8, 1, 8) HTMSP_PL(8, 2, 8) HTMSP_PL(8, 4, 8) HTMSP_PL(8, 8, 16)
+  HTMSP_PL(16, 1, 16) HTMSP_PL(16, 2, 16) HTMSP_PL(16, 4, 16)
+#undef HTMSP_PL
+  return nullptr;
+}
+
+size_t persistent_local_exchange_bytes(uint32_t C) {
+  return (size_t)2 * kPersistMaxReplicas * persistent_exchange_entries(C) * sizeof(uint16_t);
 }
 
 }  // namespace htmsp

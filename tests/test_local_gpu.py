@@ -60,6 +60,94 @@ def test_step_local(name):
     assert np.array_equal(act.cpu().numpy(), e_act)
     assert np.array_equal(pool.perm.cpu().numpy().astype(np.float64), e_perm)
     assert e_act.sum() > 0
+    assert pool.local_kernel == "k_sp_persistent_local"
+    pool.close()
+
+
+def run_local_gpu(w, grid_w, radius, learn=True, want_ov=True, cuts=()):
+    """sp_step_local over the frames, split at `cuts` into consecutive calls."""
+    import torch
+    cfg = w.cfg
+    pool = sp.SpatialPooler(cfg, w.idx, w.perm)
+    frames = torch.from_numpy(np.ascontiguousarray(w.frames).view(np.int32)).cuda()
+    F, C = w.frames.shape[0], cfg["num_columns"]
+    ov = torch.full((F, C), -1, dtype=torch.int32, device="cuda")
+    act = torch.full((F, C), 7, dtype=torch.uint8, device="cuda")
+    b = [0, *cuts, F]
+    for a0, a1 in zip(b[:-1], b[1:]):
+        sp.sp_step_local(pool.handle, cfg, frames[a0:a1], learn, grid_w, radius,
+                         ov[a0:a1] if want_ov else None, act[a0:a1])
+    pool.sync()
+    out = (ov.cpu().numpy(), act.cpu().numpy(), pool.perm.cpu().numpy(), pool.local_kernel)
+    pool.close()
+    return out
+
+
+# (N, C, S, m, n, grid_w, radius, frames): every instance family of the
+# persistent local step (rows per column 1..16, exchange words 1..16), 2-D
+# grids with ragged last rows, and shapes past its limits (per-frame launches).
+LOCAL_SHAPES = [
+    (4000, 60, 40, 2, 2, 60, 5, 9), (20000, 1000, 50, 3, 4, 37, 3, 8),
+    (20000, 4096, 64, 3, 5, 4096, 40, 5), (30000, 2048, 128, 3, 3, 64, 4, 6),
+    (30000, 500, 200, 4, 3, 500, 30, 7), (50000, 1500, 256, 4, 6, 1500, 80, 6),
+    (60000, 4000, 200, 4, 5, 63, 2, 4), (80000, 512, 300, 5, 4, 23, 6, 6),
+    (90000, 2048, 400, 5, 3, 2048, 100, 4), (100000, 300, 1024, 8, 4, 17, 2, 5),
+    (100000, 1024, 700, 8, 6, 1024, 80, 4), (20000, 5000, 16, 1, 3, 100, 2, 4),
+    (20000, 200, 1100, 8, 2, 200, 10, 3),
+]
+
+
+@pytest.mark.parametrize("shape", LOCAL_SHAPES,
+                         ids=[f"C{s[1]}_S{s[2]}_w{s[5]}_r{s[6]}" for s in LOCAL_SHAPES])
+def test_step_local_shapes(shape):
+    N, C, S, m, n, grid_w, radius, F = shape
+    cfg = synth.sp_config(N, C, S, m, n)
+    w = synth.random_instance(5000 + C + S, cfg, frames=F, density=0.1)
+    ov, act, perm, kern = run_local_gpu(w, grid_w, radius)
+    e_ov, e_act, e_perm = oracle.run_local(cfg, w.idx, w.perm, w.frames, grid_w, radius, n)
+    assert np.array_equal(ov, e_ov)
+    assert np.array_equal(act, e_act)
+    assert np.array_equal(perm.astype(np.float64), e_perm)
+    assert kern == ("plain" if C > 4096 or S > 1024 else "k_sp_persistent_local")
+
+
+def test_step_local_learning_off_and_no_overlaps():
+    w = synth.workload_paper_scale(frames=9, columns=1024, synapses=256)
+    w.cfg["winners"] = 6
+    ov, act, perm, _ = run_local_gpu(w, 1024, 80, learn=False, want_ov=False)
+    e_ov, e_act, e_perm = oracle.run_local(w.cfg, w.idx, w.perm, w.frames, 1024, 80, 6,
+                                           learn=False)
+    assert np.array_equal(act, e_act)
+    assert (ov == -1).all()
+    assert np.array_equal(perm.astype(np.float64), e_perm)
+
+
+def test_step_local_split_and_interleaved_with_global():
+    """Consecutive local calls (one of a single frame), then a global step on
+    the same handle, then local again: each path keeps its own exchange
+    sequence, and the state carries over exactly."""
+    import torch
+    w = synth.workload_paper_scale(frames=14, columns=1024, synapses=256)
+    cfg = dict(w.cfg)
+    cfg["winners"] = 6
+    pool = sp.SpatialPooler(cfg, w.idx, w.perm)
+    frames = torch.from_numpy(w.frames.view(np.int32)).cuda()
+    C = cfg["num_columns"]
+    act = torch.empty((14, C), dtype=torch.uint8, device="cuda")
+    win = torch.empty((4, cfg["winners"]), dtype=torch.int32, device="cuda")
+    sp.sp_step_local(pool.handle, cfg, frames[0:1], True, 1024, 80, None, act[0:1])
+    sp.sp_step_local(pool.handle, cfg, frames[1:6], True, 1024, 80, None, act[1:6])
+    sp.sp_step(pool.handle, cfg, frames[6:10], True, None, win)
+    sp.sp_step_local(pool.handle, cfg, frames[10:14], True, 1024, 80, None, act[10:14])
+    pool.sync()
+    _, a1, p1 = oracle.run_local(cfg, w.idx, w.perm, w.frames[0:6], 1024, 80, 6)
+    _, wg, p2 = oracle.run(cfg, w.idx, p1.astype(np.float32), w.frames[6:10])
+    _, a3, p3 = oracle.run_local(cfg, w.idx, p2.astype(np.float32), w.frames[10:14], 1024, 80, 6)
+    got = act.cpu().numpy()
+    assert np.array_equal(got[0:6], a1)
+    assert np.array_equal(win.cpu().numpy(), wg)
+    assert np.array_equal(got[10:14], a3)
+    assert np.array_equal(pool.perm.cpu().numpy().astype(np.float64), p3)
     pool.close()
 
 

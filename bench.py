@@ -548,7 +548,8 @@ def bench_boost(args, torch, sp, synth):
                    "frames_per_step": F, "path": "boost"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_overlap_plain + k_topk_plain + k_learn_plain + k_boost_update",
+                     "kernel": (pool.boost_kernel if pool.boost_kernel != "plain" else
+                                "k_overlap_plain + k_topk_plain + k_learn_plain + k_boost_update"),
                      "kernel_ms_per_launch": call_ms, "algorithmic_bytes_per_launch": abytes,
                      "counter_bytes_per_launch": None},
         "cpu_baseline": cpu,

@@ -182,8 +182,10 @@ typedef struct sp_boost_config {
 
 /* Frames in order with boosting: boosted overlap, global top-k of the
  * boosted overlaps (ties to the lower index), and with learn != 0 the
- * winners' learning and the duty-cycle/boost/raise update; one launch
- * sequence per frame.  The boost state lives in the handle (allocated on
+ * winners' learning and the duty-cycle/boost/raise update; one persistent
+ * launch for all frames where the shape allows it (C <= 1024, S <= 1024,
+ * see sp_step_boost_kernel), else one launch sequence per frame, with the
+ * same results.  The boost state lives in the handle (allocated on
  * first use, duty cycles 0 and boosts 1) and carries over between calls;
  * learn = 0 leaves it and the permanences unchanged.  overlaps_dev, if not
  * NULL, receives the boosted overlaps in 1/256 units. */
@@ -284,6 +286,12 @@ int sp_step_kernel(const sp_handle* h);
  * SP_KERNEL_PLAIN (three launches a frame) or SP_KERNEL_PERSISTENT_WAVE (one
  * persistent launch, a column group per wave); negative on a bad handle. */
 int sp_step_local_kernel(const sp_handle* h);
+
+/* Which execution sp_step_boost uses for this handle's shape on its device:
+ * SP_KERNEL_PLAIN (five launches a frame) or SP_KERNEL_PERSISTENT_WAVE (one
+ * persistent launch, a column group per wave, C <= 1024); negative on a bad
+ * handle. */
+int sp_step_boost_kernel(const sp_handle* h);
 
 /* Synchronises `stream` and reports a device-side failure of an earlier
  * step on this handle (SP_EDEVICE, after which the handle is SP_EBROKEN). */

@@ -28,7 +28,7 @@ __all__ = [
     "sp_workspace_bytes", "sp_check_state_host", "sp_create", "sp_check_state", "sp_step",
     "sp_step_plain", "sp_infer", "sp_step_many", "sp_set_histogram", "sp_encode",
     "sp_inhibit_local", "sp_step_local", "sp_step_boost", "sp_boost_state", "sp_boost_reset",
-    "sp_encoded_bits", "sp_step_is_persistent", "sp_step_kernel", "sp_step_local_kernel", "STEP_KERNELS",
+    "sp_encoded_bits", "sp_step_is_persistent", "sp_step_kernel", "sp_step_local_kernel", "sp_step_boost_kernel", "STEP_KERNELS",
     "sp_sync",
     "sp_destroy",
     "sp_last_error", "SP_OK", "SP_EINVAL", "SP_ENOMEM", "SP_EDEVICE", "SP_EBROKEN",
@@ -298,6 +298,12 @@ def sp_step_local_kernel(h: int) -> str:
     return "k_sp_persistent_local" if code == 2 else "plain"
 
 
+def sp_step_boost_kernel(h: int) -> str:
+    """The execution sp_step_boost uses: "plain" or "k_sp_persistent_boost"."""
+    code = _check(lib().sp_step_boost_kernel(ctypes.c_void_p(h)), "sp_step_boost_kernel")
+    return "k_sp_persistent_boost" if code == 2 else "plain"
+
+
 def sp_sync(h: int, stream=None) -> None:
     _check(lib().sp_sync(ctypes.c_void_p(h), _stream(stream)), "sp_sync")
 
@@ -342,6 +348,11 @@ class SpatialPooler:
     def local_kernel(self) -> str:
         """The execution sp_step_local uses."""
         return sp_step_local_kernel(self.handle)
+
+    @property
+    def boost_kernel(self) -> str:
+        """The execution sp_step_boost uses."""
+        return sp_step_boost_kernel(self.handle)
 
     def step(self, frames, learn: bool = True, overlaps: bool = True, plain: bool = False,
              stream=None):

@@ -82,6 +82,7 @@ SIGNATURES = [
     ("sp_step_is_persistent", ctypes.c_int, [P]),
     ("sp_step_kernel", ctypes.c_int, [P]),
     ("sp_step_local_kernel", ctypes.c_int, [P]),
+    ("sp_step_boost_kernel", ctypes.c_int, [P]),
     ("sp_sync", ctypes.c_int, [P, P]),
     ("sp_destroy", ctypes.c_int, [P]),
     ("sp_last_error", ctypes.c_char_p, []),

@@ -46,6 +46,8 @@ struct sp_handle {
   // grid, its exchange and the count of exchanges it has used
   const void* lkernel;
   uint32_t lgrid;
+  const void* bkernel;  // persistent boosted step (null: per-frame launches)
+  uint32_t bgrid;
   uint64_t* xloc;
   uint64_t xloc_frames;
   bool broken;
@@ -200,6 +202,7 @@ uint32_t next_pow2(uint32_t x) {
 void plan_persistent(sp_handle* h) {
   h->persistent = false;
   h->lkernel = nullptr;
+  h->bkernel = nullptr;
   int dev = h->device, cus = 0, coop = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return;
   if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess) return;
@@ -209,6 +212,22 @@ void plan_persistent(sp_handle* h) {
     return;
   const uint32_t rpc = next_pow2((sh.S + 63) / 64);
   const uint32_t nv = next_pow2(htmsp::persistent_exchange_entries(sh.C) / 256);
+  // The boosted step: a column group per wave, every wave holding every
+  // column's duty cycles (C <= kBoostPersistMaxColumns).
+  if (sh.C <= htmsp::kBoostPersistMaxColumns) {
+    const uint32_t rw = std::max(4u, rpc);
+    const uint32_t cols = rw / rpc * htmsp::kPersistWaves;
+    const uint32_t grid = (sh.C + cols - 1) / cols;
+    const void* kb = htmsp::persistent_boost_kernel(rpc, nv);
+    int per_cu = 0;
+    if (kb && grid <= (uint32_t)cus &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kb, htmsp::kPersistWaves * 64, 0) ==
+            hipSuccess &&
+        per_cu >= 1) {
+      h->bkernel = kb;
+      h->bgrid = grid;
+    }
+  }
   // The local-inhibition step: the same column split, one workgroup per CU.
   for (uint32_t rw = std::max(4u, rpc); rw <= 16; rw *= 2) {
     const uint32_t cols = rw / rpc * htmsp::kPersistWaves;
@@ -860,6 +879,32 @@ int sp_step_boost(sp_handle* h, const sp_boost_config* bc, const uint32_t* frame
   const htmsp::BoostParams bp = {bc->period_log2, bc->min_pct_q16, bc->max_boost_q8,
                                  bc->bump_q8};
   if (learn) ++h->state_version;
+  if (h->bkernel) {
+    htmsp::BoostArgs a;
+    a.idx = h->idx;
+    a.perm = h->perm;
+    a.frames = frames_dev;
+    a.ov_out = overlaps_dev;
+    a.win_out = winners_dev;
+    a.xchg = h->xloc;
+    a.err = h->err;
+    a.adc = adc;
+    a.odc = odc;
+    a.boost = boost;
+    a.F = num_frames;
+    a.learn = learn ? 1u : 0u;
+    a.frame_base = (uint32_t)h->xloc_frames;
+    a.replicas = htmsp::kPersistReplicas;
+    a.spin_limit = kSpinLimit;
+    a.b = bp;
+    a.sh = sh;
+    void* args[] = {&a};
+    hipError_t e = hipLaunchCooperativeKernel(h->bkernel, dim3(h->bgrid),
+                                              dim3(htmsp::kPersistWaves * 64), args, 0, s);
+    if (e != hipSuccess) return hip_fail(e, "persistent boosted step launch");
+    h->xloc_frames += num_frames;
+    return add_histogram(h, winners_dev, num_frames, s);
+  }
   for (uint32_t t = 0; t < num_frames; ++t) {
     const uint32_t* frame = frames_dev + (size_t)t * sh.W;
     int32_t* ov = overlaps_dev ? overlaps_dev + (size_t)t * sh.C : h->ov_scratch;
@@ -941,6 +986,11 @@ int sp_set_histogram(sp_handle* h, uint32_t* hist_dev) {
 int sp_step_is_persistent(const sp_handle* h) {
   if (!h) return fail(SP_EINVAL, "handle is NULL");
   return h->persistent ? 1 : 0;
+}
+
+int sp_step_boost_kernel(const sp_handle* h) {
+  if (!h) return fail(SP_EINVAL, "handle is NULL");
+  return h->bkernel ? SP_KERNEL_PERSISTENT_WAVE : SP_KERNEL_PLAIN;
 }
 
 int sp_step_local_kernel(const sp_handle* h) {

@@ -86,6 +86,382 @@ __global__ __launch_bounds__(256) void k_boost_init(uint32_t* __restrict__ adc,
   boost[c] = 256;
 }
 
+// Persistent boosted learning step, the order of a frame as in the launch
+// sequence above: boosted overlaps with the current boosts, global top-k of
+// the boosted values (ties to the lower index), learning on the winners, duty
+// cycles, minimum, boosts, permanence raise.  Columns are split as in the
+// other persistent kernels (kPersistWaves waves per workgroup, a column
+// group per wave, synapses in registers).  Per frame every wave publishes
+// its columns' gated overlaps through a tagged exchange; wave 0 of each
+// workgroup reads all of them into LDS; then every wave holds, for the
+// columns u * 256 + 4 * lane + q of its lane (u < NV, q < 4), their gated
+// overlap, duty cycles and boost, resolves the top-k of the boosted values
+// and updates every column's duty cycles and boost itself, so that no second
+// exchange is needed for the maximum duty cycle.  Global wave 0 writes the
+// frame's winners and boosted overlaps and, at the end, the duty cycles and
+// boosts.
+template <bool B>
+struct BoostRole {
+  static constexpr bool value = B;
+};
+
+// Columns of the lane whose boosted value is >= x, summed over the wave.
+template <int N>
+__device__ __forceinline__ uint32_t count_ge32(const uint32_t (&bv)[N], uint32_t x) {
+  uint32_t n = 0;
+#pragma unroll
+  for (int i = 0; i < N; ++i) n += bv[i] >= x ? 1u : 0u;
+  return wave_count<ilog2(N) + 1>(n);
+}
+
+// T = the largest x >= 1 with #(value >= x) >= k (0 when fewer than k
+// values are positive), *c_hi = #(value >= T + 1); a gallop from `guess`,
+// then a binary search (the same search as the 16-bit packed form).
+template <int N>
+__device__ __forceinline__ uint32_t topk_threshold32(const uint32_t (&bv)[N], uint32_t vmax,
+                                                     uint32_t k, uint32_t guess,
+                                                     uint32_t* c_hi_out) {
+  uint32_t lo = 0, hi = vmax, c_hi = 0;
+  const uint32_t g0 = min(max(guess, 1u), vmax);
+  const uint32_t c0 = count_ge32(bv, g0);
+  if (c0 >= k) {
+    lo = g0;
+    for (uint32_t step = 1; lo < hi; step <<= 1) {
+      const uint32_t x = hi - lo > step ? lo + step : hi;
+      const uint32_t cx = count_ge32(bv, x);
+      if (cx >= k) {
+        lo = x;
+      } else {
+        hi = x - 1;
+        c_hi = cx;
+        break;
+      }
+    }
+  } else {
+    hi = g0 - 1;
+    c_hi = c0;
+    for (uint32_t step = 1; hi > 0; step <<= 1) {
+      const uint32_t x = hi >= step ? hi - step + 1 : 1u;
+      const uint32_t cx = count_ge32(bv, x);
+      if (cx >= k) {
+        lo = x;
+        break;
+      }
+      hi = x - 1;
+      c_hi = cx;
+    }
+  }
+  while (lo < hi) {
+    const uint32_t mid = lo + (hi - lo + 1) / 2;
+    const uint32_t c = count_ge32(bv, mid);
+    if (c >= k) {
+      lo = mid;
+    } else {
+      hi = mid - 1;
+      c_hi = c;
+    }
+  }
+  *c_hi_out = c_hi;
+  return lo;
+}
+
+template <int RPC, int NV>
+__global__ __launch_bounds__(kPersistWaves * kWave) void k_sp_persistent_boost(BoostArgs a) {
+  constexpr uint32_t RW = RPC > 4 ? RPC : 4;
+  constexpr uint32_t CPW = RW / RPC;
+  constexpr uint32_t WGC = kPersistWaves * CPW;
+  constexpr uint32_t NC = 4 * NV;  // columns per lane
+  constexpr uint32_t kSeenAbort = 0xFFFFFFFFu;
+  __shared__ uint64_t xl[2][NV * kWave];
+  __shared__ uint32_t pub[WGC];
+  __shared__ uint32_t seen;
+  const Shape sh = a.sh;
+  const BoostParams b = a.b;
+  const uint32_t lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  const uint32_t gw = blockIdx.x * kPersistWaves + wave;
+  const uint32_t c_begin = gw * CPW;
+  const uint32_t wg_begin = blockIdx.x * WGC;
+  const uint32_t ncols = c_begin < sh.C ? min(CPW, sh.C - c_begin) : 0u;
+  const uint32_t vmax = sh.S * b.max_boost_q8;
+  const uint64_t P1 = (1ull << b.period_log2) - 1ull;
+  if (threadIdx.x == 0) seen = 0;
+
+  uint32_t st[RW], msk[RW], wi[RW];
+  uint32_t row_ok = 0;
+#pragma unroll
+  for (uint32_t r = 0; r < RW; ++r) {
+    const uint32_t j = r / RPC, s = (r % RPC) * kWave + lane;
+    const bool ok = j < ncols && s < sh.S;
+    const size_t off = ok ? (size_t)(c_begin + j) * sh.S + s : 0;
+    const uint32_t i = min(a.idx[off], sh.N - 1);
+    const uint32_t q = perm_to_q(a.perm[off]);
+    st[r] = ok ? (i << 9) | q : 0u;
+    msk[r] = (ok && q >= sh.theta) ? (1u << (i & 31u)) : 0u;
+    wi[r] = ok ? i >> 5 : 0u;
+    row_ok |= ok ? 1u << r : 0u;
+  }
+  // Every column's duty cycles and boost, in the exchange's column order.
+  uint32_t adc[NC], odc[NC], bst[NC];
+#pragma unroll
+  for (uint32_t i = 0; i < NC; ++i) {
+    const uint32_t c = (i / 4) * 4 * kWave + 4 * lane + i % 4;
+    adc[i] = c < sh.C ? a.adc[c] : 0u;
+    odc[i] = c < sh.C ? a.odc[c] : 0u;
+    bst[i] = c < sh.C ? a.boost[c] : 256u;
+  }
+  const uint32_t rep = xcc_id() % a.replicas;
+  uint32_t guess = 1 + vmax / 16;
+  bool abort = false;
+
+  auto gather = [&](uint32_t t, uint32_t (&x)[RW]) {
+    const uint32_t* f = a.frames + (size_t)min(t, a.F - 1) * sh.W;
+#pragma unroll
+    for (uint32_t r = 0; r < RW; ++r) x[r] = f[wi[r]];
+  };
+  auto overlaps = [&](uint32_t cols, const uint32_t (&x)[RW], uint32_t (&o)[CPW]) {
+#pragma unroll
+    for (uint32_t j = 0; j < CPW; ++j) {
+      if ((cols >> j) & 1u) {
+        uint32_t c = 0;
+#pragma unroll
+        for (uint32_t rr = 0; rr < RPC; ++rr) {
+          const uint32_t r = j * RPC + rr;
+          c += (uint32_t)__popcll(__ballot((x[r] & msk[r]) != 0u));
+        }
+        o[j] = (j < ncols && c >= sh.m) ? c : 0u;
+      }
+    }
+  };
+  // Bit (4u + q) of this lane's mask `m`, for column c of the frame order.
+  auto column_bit = [&](uint32_t m, uint32_t c) {
+    const uint32_t src = (c % (4 * kWave)) / 4;
+    return ((uint32_t)__shfl((int)m, (int)src) >> ((c / (4 * kWave)) * 4 + c % 4)) & 1u;
+  };
+
+  auto run = [&](auto role) {
+    constexpr bool POLL = decltype(role)::value;
+    uint32_t w[RW], o[CPW];
+    gather(0, w);
+    overlaps((1u << CPW) - 1u, w, o);
+    if (lane < CPW) pub[wave * CPW + lane] = lane_value(o, lane);
+    __syncthreads();
+    for (uint32_t t = 0; t < a.F; ++t) {
+      const uint32_t g = a.frame_base + t;
+      const uint32_t slot = g & 1u;
+      const uint32_t tg = ((g + 1u) & 3u) << kTagShift;
+      uint64_t* xs = a.xchg + (size_t)(rep * 2 + slot) * NV * kWave;
+      if (!POLL && wave == 1 && lane < WGC / 4) {
+        const uint64_t word = (uint64_t)(tg | pub[4 * lane]) |
+                              ((uint64_t)(tg | pub[4 * lane + 1]) << 16) |
+                              ((uint64_t)(tg | pub[4 * lane + 2]) << 32) |
+                              ((uint64_t)(tg | pub[4 * lane + 3]) << 48);
+        for (uint32_t rr = 0; rr < a.replicas; ++rr)
+          store_word(a.xchg + (size_t)(rr * 2 + slot) * NV * kWave + wg_begin / 4 + lane, word);
+      }
+      uint32_t nx[RW], on[CPW];
+      gather(t + 1, nx);
+      overlaps((1u << CPW) - 1u, nx, on);  // speculation: no own column changes
+
+      uint64_t v[NV];
+      if constexpr (POLL) {
+#pragma unroll
+        for (int u = 0; u < NV; ++u) v[u] = load_entries(xs + u * kWave + lane);
+        const uint64_t tagw = (uint64_t)tg * kOnes16;
+        uint32_t spins = 0;
+        while (true) {
+          bool ok = true;
+#pragma unroll
+          for (int u = 0; u < NV; ++u) ok = ok && ((v[u] ^ tagw) & tag_mask(u, lane, sh.C)) == 0ull;
+          if (__all(ok)) break;
+          if (++spins > a.spin_limit || ((spins & 63u) == 0 && load_tagged(a.err) != 0)) {
+            abort = true;
+            break;
+          }
+#pragma unroll
+          for (int u = 0; u < NV; ++u)
+            if (((v[u] ^ tagw) & tag_mask(u, lane, sh.C)) != 0ull)
+              v[u] = load_entries(xs + u * kWave + lane);
+        }
+        if (abort) {
+          lds_release(&seen, kSeenAbort);
+          break;
+        }
+#pragma unroll
+        for (int u = 0; u < NV; ++u) xl[t & 1][u * kWave + lane] = v[u];
+        lds_release(&seen, t + 1);
+      } else {
+        // Bounded by wave 0, which sets `seen` within its own spin limit.
+        uint32_t sv;
+        while ((sv = lds_acquire(&seen)) <= t) __builtin_amdgcn_s_sleep(0);
+        if (sv == kSeenAbort) {
+          abort = true;
+          break;
+        }
+#pragma unroll
+        for (int u = 0; u < NV; ++u) v[u] = xl[t & 1][u * kWave + lane];
+      }
+
+      // Boosted values and the frame's top-k.
+      uint32_t gv[NC], bv[NC];
+#pragma unroll
+      for (uint32_t i = 0; i < NC; ++i) {
+        const uint32_t c = (i / 4) * 4 * kWave + 4 * lane + i % 4;
+        gv[i] = c < sh.C ? (uint32_t)(v[i / 4] >> (16 * (i % 4))) & 0x3FFFu : 0u;
+        bv[i] = gv[i] * bst[i];
+      }
+      uint32_t c_hi;
+      const uint32_t T = topk_threshold32(bv, vmax, sh.k, guess, &c_hi);
+      if (T) guess = T;
+      const uint32_t need = T ? sh.k - c_hi : 0u;
+      const uint32_t nsel = T ? sh.k : c_hi;
+      // Winners in column order: every value above T, then the first `need`
+      // equal to T; `sel` holds bit 4u + q for column u * 256 + 4 * lane + q.
+      uint32_t sel = 0, eq_before = 0, sel_before = 0;
+      int32_t* wrow = a.win_out + (size_t)t * sh.k;
+#pragma unroll
+      for (uint32_t u = 0; u < NV; ++u) {
+        uint32_t gt = 0, eq = 0;
+#pragma unroll
+        for (uint32_t q = 0; q < 4; ++q) {
+          gt |= bv[4 * u + q] > T ? 1u << q : 0u;
+          eq |= (T != 0 && bv[4 * u + q] == T) ? 1u << q : 0u;
+        }
+        const uint32_t neq = (uint32_t)__popc(eq);
+        const uint32_t pre = eq_before + wave_prefix<3>(neq, lane);
+        uint32_t keep = need > pre ? need - pre : 0u, take = 0;
+#pragma unroll
+        for (uint32_t q = 0; q < 4; ++q) {
+          const bool use = ((eq >> q) & 1u) && keep > 0;
+          take |= use ? 1u << q : 0u;
+          keep -= use ? 1u : 0u;
+        }
+        eq_before += wave_count<3>(neq);
+        const uint32_t su = gt | take;
+        sel |= su << (4 * u);
+        if (gw == 0) {
+          uint32_t pos = sel_before + wave_prefix<3>((uint32_t)__popc(su), lane);
+#pragma unroll
+          for (uint32_t q = 0; q < 4; ++q)
+            if ((su >> q) & 1u) wrow[pos++] = (int32_t)(u * 4 * kWave + 4 * lane + q);
+          sel_before += wave_count<3>((uint32_t)__popc(su));
+        }
+      }
+      if (gw == 0) {
+        for (uint32_t i = nsel + lane; i < sh.k; i += kWave) wrow[i] = -1;
+        if (a.ov_out) {
+#pragma unroll
+          for (uint32_t i = 0; i < NC; ++i) {
+            const uint32_t c = (i / 4) * 4 * kWave + 4 * lane + i % 4;
+            if (c < sh.C) a.ov_out[(size_t)t * sh.C + c] = (int32_t)bv[i];
+          }
+        }
+      }
+
+      uint32_t changed = 0;
+      if (a.learn) {
+        // Learning on the own columns that won, with frame t.
+        uint32_t won = 0;
+#pragma unroll
+        for (uint32_t j = 0; j < CPW; ++j)
+          won |= (j < ncols && column_bit(sel, c_begin + j)) ? 1u << j : 0u;
+#pragma unroll
+        for (uint32_t r = 0; r < RW; ++r) {
+          if ((won >> (r / RPC)) & (row_ok >> r) & 1u) {
+            const uint32_t i = st[r] >> 9;
+            const uint32_t q = learn_q(st[r] & 511u, input_bit(w[r], i), sh);
+            st[r] = (i << 9) | q;
+            msk[r] = q >= sh.theta ? 1u << (i & 31u) : 0u;
+          }
+        }
+        // Duty cycles of every column, their maximum, the minimum, boosts.
+        uint32_t mx = 0;
+#pragma unroll
+        for (uint32_t i = 0; i < NC; ++i) {
+          adc[i] = (uint32_t)(((uint64_t)adc[i] * P1 + (((sel >> i) & 1u) ? 65536u : 0u)) >>
+                              b.period_log2);
+          odc[i] = (uint32_t)(((uint64_t)odc[i] * P1 + (gv[i] > 0 ? 65536u : 0u)) >>
+                              b.period_log2);
+          mx = max(mx, adc[i]);
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, off));
+        const uint32_t mn = (uint32_t)(((uint64_t)mx * b.min_pct_q16) >> 16);
+        // (max_boost - 256)(mn - a) / mn, exactly: a double estimate (within
+        // one of the quotient for numerators below 2^28), then corrected.
+        const double rmn = mn ? 1.0 / (double)mn : 0.0;
+        uint32_t raise = 0;
+#pragma unroll
+        for (uint32_t i = 0; i < NC; ++i) {
+          uint32_t nb = 256u;
+          if (mn != 0 && adc[i] < mn) {
+            const uint32_t num = (b.max_boost_q8 - 256u) * (mn - adc[i]);
+            uint32_t qt = (uint32_t)((double)num * rmn);
+            qt = (uint64_t)qt * mn > num ? qt - 1u : qt;
+            qt = (uint64_t)(qt + 1u) * mn <= num ? qt + 1u : qt;
+            nb = 256u + qt;
+          }
+          bst[i] = nb;
+          raise |= (odc[i] < mn) ? 1u << i : 0u;
+        }
+        // Permanence raise of the own columns whose overlap duty is below it.
+        if (b.bump_q8) {
+          uint32_t up = 0;
+#pragma unroll
+          for (uint32_t j = 0; j < CPW; ++j)
+            up |= (j < ncols && column_bit(raise, c_begin + j)) ? 1u << j : 0u;
+#pragma unroll
+          for (uint32_t r = 0; r < RW; ++r) {
+            if ((up >> (r / RPC)) & (row_ok >> r) & 1u) {
+              const uint32_t i = st[r] >> 9;
+              const uint32_t q = min((st[r] & 511u) + b.bump_q8, 256u);
+              st[r] = (i << 9) | q;
+              msk[r] = q >= sh.theta ? 1u << (i & 31u) : 0u;
+            }
+          }
+          changed = won | up;
+        } else {
+          changed = won;
+        }
+      }
+      if (changed) overlaps(changed, nx, on);
+#pragma unroll
+      for (uint32_t r = 0; r < RW; ++r) w[r] = nx[r];
+#pragma unroll
+      for (uint32_t j = 0; j < CPW; ++j) o[j] = on[j];
+      if (lane < CPW) pub[wave * CPW + lane] = lane_value(o, lane);
+      __syncthreads();
+    }
+  };
+  if (a.F > 0) {
+    if (wave == 0)
+      run(BoostRole<true>{});
+    else
+      run(BoostRole<false>{});
+  }
+  if (abort) {
+    if (wave == 0 && lane == 0) store_tagged(a.err, 1u);
+    return;
+  }
+  if (a.learn) {
+#pragma unroll
+    for (uint32_t r = 0; r < RW; ++r) {
+      const uint32_t j = r / RPC, s = (r % RPC) * kWave + lane;
+      if ((row_ok >> r) & 1u) a.perm[(size_t)(c_begin + j) * sh.S + s] = q_to_perm(st[r] & 511u);
+    }
+    if (gw == 0) {
+#pragma unroll
+      for (uint32_t i = 0; i < NC; ++i) {
+        const uint32_t c = (i / 4) * 4 * kWave + 4 * lane + i % 4;
+        if (c < sh.C) {
+          a.adc[c] = adc[i];
+          a.odc[c] = odc[i];
+          a.boost[c] = bst[i];
+        }
+      }
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t launch_boost_update(const int32_t* ov, const int32_t* winners, const Shape& sh,
@@ -104,6 +480,16 @@ hipError_t launch_boost_init(uint32_t* adc, uint32_t* odc, uint32_t* boost, uint
                              hipStream_t s) {
   hipLaunchKernelGGL(k_boost_init, dim3((C + 255) / 256), dim3(256), 0, s, adc, odc, boost, C);
   return hipGetLastError();
+}
+
+const void* persistent_boost_kernel(uint32_t rpc, uint32_t nv) {
+#define HTMSP_PB(P, V) \
+  if (rpc == P && nv == V) return reinterpret_cast<const void*>(&k_sp_persistent_boost<P, V>);
+  HTMSP_PB(1, 1) HTMSP_PB(1, 2) HTMSP_PB(1, 4) HTMSP_PB(2, 1) HTMSP_PB(2, 2) HTMSP_PB(2, 4)
+  HTMSP_PB(4, 1) HTMSP_PB(4, 2) HTMSP_PB(4, 4) HTMSP_PB(8, 1) HTMSP_PB(8, 2) HTMSP_PB(8, 4)
+  HTMSP_PB(16, 1) HTMSP_PB(16, 2) HTMSP_PB(16, 4)
+#undef HTMSP_PB
+  return nullptr;
 }
 
 }  // namespace htmsp

@@ -138,6 +138,30 @@ hipError_t launch_boost_update(const int32_t* ov, const int32_t* winners, const 
                                uint32_t* boost, uint8_t* raise, float* perm, hipStream_t s);
 hipError_t launch_boost_init(uint32_t* adc, uint32_t* odc, uint32_t* boost, uint32_t C,
                              hipStream_t s);
+// Persistent boosted learning step: F frames in one cooperative launch, one
+// exchange of every column's gated overlap per frame (the local step's
+// exchange region and tag sequence).
+struct BoostArgs {
+  const uint32_t* idx;
+  float* perm;
+  const uint32_t* frames;
+  int32_t* ov_out;   // [F][C] boosted overlaps, or null
+  int32_t* win_out;  // [F][k]
+  uint64_t* xchg;
+  uint32_t* err;
+  uint32_t* adc;     // [C] active duty cycles (1/65536), updated in place
+  uint32_t* odc;     // [C] overlap duty cycles
+  uint32_t* boost;   // [C] boosts (1/256)
+  uint32_t F, learn, frame_base, replicas, spin_limit;
+  BoostParams b;
+  Shape sh;
+};
+// Largest C of the persistent boosted step (every wave keeps every column's
+// duty cycles and boost in registers).
+constexpr uint32_t kBoostPersistMaxColumns = 1024;
+// The persistent boosted instance for `rpc` rows per column and `nv`
+// exchange words per lane (rows per wave max(4, rpc)); nullptr otherwise.
+const void* persistent_boost_kernel(uint32_t rpc, uint32_t nv);
 
 // Local inhibition (sp_local.hip): active [F][C] from overlaps [F][C].
 hipError_t launch_inhibit_local(const int32_t* ov, uint32_t F, uint32_t C, uint32_t grid_w,

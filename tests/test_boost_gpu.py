@@ -95,3 +95,69 @@ def test_learning_off_and_reset():
     adc, odc, boost = _state(pool, 256)
     assert adc.max() == 0 and odc.max() == 0 and np.all(boost == 256)
     pool.close()
+
+
+# (N, C, S, m, k, boost config, frames): every instance family of the
+# persistent boosted step (rows per column 1..16, exchange words 1..4), no
+# minimum (min_pct 0), no raise (bump 0), and shapes past its limits.
+BOOST_SHAPES = [
+    (3000, 40, 30, 2, 5, BC, 12), (9000, 300, 64, 3, 12, BC, 10),
+    (20000, 1000, 50, 3, 30, BC, 10), (20000, 700, 128, 3, 20, BC, 8),
+    (30000, 1024, 256, 4, 40, {**BC, "min_pct_q16": 0}, 8),
+    (60000, 500, 400, 5, 15, {**BC, "bump_q8": 0}, 8),
+    (80000, 256, 1000, 8, 10, {**BC, "max_boost_q8": 4096, "period_log2": 3}, 8),
+    (20000, 2000, 40, 2, 50, BC, 6), (20000, 100, 1100, 8, 4, BC, 5),
+]
+
+
+@pytest.mark.parametrize("shape", BOOST_SHAPES,
+                         ids=[f"C{s[1]}_S{s[2]}_{i}" for i, s in enumerate(BOOST_SHAPES)])
+def test_shapes_and_parameters(shape):
+    N, C, S, m, k, bc, F = shape
+    cfg = synth.sp_config(N, C, S, m, k)
+    w = synth.random_instance(7000 + C + S, cfg, frames=F, density=0.1)
+    pool = sp.SpatialPooler(cfg, w.idx, w.perm)
+    want = "k_sp_persistent_boost" if C <= 1024 and S <= 1024 else "plain"
+    assert pool.boost_kernel == want
+    ov, win = _run(pool, cfg, bc, w.frames)
+    e_ov, e_win, e_perm, e_state = oracle.run_boost(cfg, bc, w.idx, w.perm, w.frames)
+    _same(ov, e_ov, "boosted overlaps")
+    _same(win, e_win, "winners")
+    _same(pool.perm.cpu().numpy().astype(np.float64), e_perm, "permanences")
+    for got, want_s, what in zip(_state(pool, C), e_state, ("active duty", "overlap duty", "boost")):
+        _same(got, want_s, what)
+    pool.close()
+
+
+def test_interleaved_with_local_and_global_steps():
+    """Boosted, local and global steps on one handle: the boosted and local
+    steps share one exchange sequence, the global step has its own."""
+    import torch
+    w = synth.workload_paper_scale(frames=16, columns=1024, synapses=256)
+    cfg = dict(w.cfg)
+    pool = sp.SpatialPooler(cfg, w.idx, w.perm)
+    frames = torch.from_numpy(w.frames.view(np.int32)).cuda()
+    C, k = cfg["num_columns"], cfg["winners"]
+    win_b = torch.empty((10, k), dtype=torch.int32, device="cuda")
+    act = torch.empty((3, C), dtype=torch.uint8, device="cuda")
+    win_g = torch.empty((3, k), dtype=torch.int32, device="cuda")
+    sp.sp_step_boost(pool.handle, cfg, BC, frames[0:5], True, None, win_b[0:5])
+    # local inhibition takes the handle's winners (40) as n
+    sp.sp_step_local(pool.handle, cfg, frames[5:8], True, 1024, 80, None, act)
+    sp.sp_step(pool.handle, cfg, frames[8:11], True, None, win_g)
+    sp.sp_step_boost(pool.handle, cfg, BC, frames[11:16], True, None, win_b[5:10])
+    pool.sync()
+    _, e_w1, p1, st1 = oracle.run_boost(cfg, BC, w.idx, w.perm, w.frames[0:5])
+    _, e_act, p2 = oracle.run_local(cfg, w.idx, p1.astype(np.float32), w.frames[5:8], 1024, 80, k)
+    _, e_wg, p3 = oracle.run(cfg, w.idx, p2.astype(np.float32), w.frames[8:11])
+    _, e_w2, p4, st2 = oracle.run_boost(cfg, BC, w.idx, p3.astype(np.float32), w.frames[11:16],
+                                        state=st1)
+    got_b = win_b.cpu().numpy()
+    _same(got_b[0:5], e_w1, "boosted winners, first call")
+    _same(act.cpu().numpy(), e_act, "local active columns")
+    _same(win_g.cpu().numpy(), e_wg, "global winners")
+    _same(got_b[5:10], e_w2, "boosted winners, second call")
+    _same(pool.perm.cpu().numpy().astype(np.float64), p4, "permanences")
+    for got, want_s, what in zip(_state(pool, C), st2, ("active duty", "overlap duty", "boost")):
+        _same(got, want_s, what)
+    pool.close()

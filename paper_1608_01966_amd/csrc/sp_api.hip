@@ -212,50 +212,39 @@ void plan_persistent(sp_handle* h) {
     return;
   const uint32_t rpc = next_pow2((sh.S + 63) / 64);
   const uint32_t nv = next_pow2(htmsp::persistent_exchange_entries(sh.C) / 256);
-  // The boosted step: a column group per wave, every wave holding every
-  // column's duty cycles (C <= kBoostPersistMaxColumns).
-  if (sh.C <= htmsp::kBoostPersistMaxColumns) {
-    const uint32_t rw = std::max(4u, rpc);
-    const uint32_t cols = rw / rpc * htmsp::kPersistWaves;
-    const uint32_t grid = (sh.C + cols - 1) / cols;
-    const void* kb = htmsp::persistent_boost_kernel(rpc, nv);
+  // The column-group-per-wave split shared by the global, local and boosted
+  // steps (each needs an instance for it, and a co-resident grid).
+  uint32_t wgrid = 0;
+  const uint32_t rw = htmsp::persistent_wave_rows(sh.C, rpc, cus, &wgrid);
+  auto fits = [&](const void* k) {
     int per_cu = 0;
-    if (kb && grid <= (uint32_t)cus &&
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kb, htmsp::kPersistWaves * 64, 0) ==
-            hipSuccess &&
-        per_cu >= 1) {
+    return k && hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, htmsp::kPersistWaves * 64,
+                                                             0) == hipSuccess &&
+           per_cu >= 1;
+  };
+  // The boosted step: every wave holds every column's duty cycles
+  // (C <= kBoostPersistMaxColumns).
+  if (rw && sh.C <= htmsp::kBoostPersistMaxColumns) {
+    const void* kb = htmsp::persistent_boost_kernel(rpc, nv, rw);
+    if (fits(kb)) {
       h->bkernel = kb;
-      h->bgrid = grid;
+      h->bgrid = wgrid;
     }
   }
-  // The local-inhibition step: the same column split, one workgroup per CU.
-  for (uint32_t rw = std::max(4u, rpc); rw <= 16; rw *= 2) {
-    const uint32_t cols = rw / rpc * htmsp::kPersistWaves;
-    const uint32_t grid = (sh.C + cols - 1) / cols;
-    if (grid > (uint32_t)cus) continue;
+  // The local-inhibition step.
+  if (rw) {
     const void* kl = htmsp::persistent_local_kernel(rpc, nv, rw);
-    int per_cu = 0;
-    if (kl && hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kl, htmsp::kPersistWaves * 64,
-                                                           0) == hipSuccess &&
-        per_cu >= 1) {
+    if (fits(kl)) {
       h->lkernel = kl;
-      h->lgrid = grid;
+      h->lgrid = wgrid;
     }
-    break;
   }
-  // One column group per wave, one workgroup per CU: the fewest rows per
-  // wave (4, 8 or 16, at least one column) that keep the grid to one
-  // workgroup per CU.
-  for (uint32_t rw = std::max(4u, rpc); rw <= 16; rw *= 2) {
-    const uint32_t cols = rw / rpc * htmsp::kPersistWaves;
-    const uint32_t grid = (sh.C + cols - 1) / cols;
-    if (grid > (uint32_t)cus) continue;
+  // The global step: the column-group-per-wave kernel where its split fits,
+  // else 16 rows per workgroup.
+  if (rw) {
     const void* kw = htmsp::persistent_wave_kernel(rpc, nv, rw);
-    int per_cu = 0;
-    if (kw && hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kw, htmsp::kPersistWaves * 64,
-                                                           0) == hipSuccess &&
-        per_cu >= 1) {
-      h->grid = grid;
+    if (fits(kw)) {
+      h->grid = wgrid;
       h->block = htmsp::kPersistWaves * 64;
       h->replicas = htmsp::kPersistReplicas;
       h->pkernel = kw;
@@ -264,7 +253,6 @@ void plan_persistent(sp_handle* h) {
       h->persistent = true;
       return;
     }
-    break;
   }
   const uint32_t rows = htmsp::kPersistRows;
   const void* k = htmsp::persistent_kernel(rpc, nv, rows);

@@ -165,9 +165,8 @@ __device__ __forceinline__ uint32_t topk_threshold32(const uint32_t (&bv)[N], ui
   return lo;
 }
 
-template <int RPC, int NV>
+template <int RPC, int NV, int RW>
 __global__ __launch_bounds__(kPersistWaves * kWave) void k_sp_persistent_boost(BoostArgs a) {
-  constexpr uint32_t RW = RPC > 4 ? RPC : 4;
   constexpr uint32_t CPW = RW / RPC;
   constexpr uint32_t WGC = kPersistWaves * CPW;
   constexpr uint32_t NC = 4 * NV;  // columns per lane
@@ -482,12 +481,15 @@ hipError_t launch_boost_init(uint32_t* adc, uint32_t* odc, uint32_t* boost, uint
   return hipGetLastError();
 }
 
-const void* persistent_boost_kernel(uint32_t rpc, uint32_t nv) {
-#define HTMSP_PB(P, V) \
-  if (rpc == P && nv == V) return reinterpret_cast<const void*>(&k_sp_persistent_boost<P, V>);
-  HTMSP_PB(1, 1) HTMSP_PB(1, 2) HTMSP_PB(1, 4) HTMSP_PB(2, 1) HTMSP_PB(2, 2) HTMSP_PB(2, 4)
-  HTMSP_PB(4, 1) HTMSP_PB(4, 2) HTMSP_PB(4, 4) HTMSP_PB(8, 1) HTMSP_PB(8, 2) HTMSP_PB(8, 4)
-  HTMSP_PB(16, 1) HTMSP_PB(16, 2) HTMSP_PB(16, 4)
+const void* persistent_boost_kernel(uint32_t rpc, uint32_t nv, uint32_t rw) {
+#define HTMSP_PB(P, V, R)                              \
+  if (rpc == P && nv == V && rw == R)                  \
+    return reinterpret_cast<const void*>(&k_sp_persistent_boost<P, V, R>);
+  // The shapes persistent_wave_rows gives on a 256-CU device.
+  HTMSP_PB(1, 1, 4) HTMSP_PB(1, 2, 4) HTMSP_PB(1, 4, 4) HTMSP_PB(2, 1, 4) HTMSP_PB(2, 2, 4)
+  HTMSP_PB(2, 4, 4) HTMSP_PB(4, 1, 4) HTMSP_PB(4, 2, 4) HTMSP_PB(4, 4, 8) HTMSP_PB(8, 1, 8)
+  HTMSP_PB(8, 2, 8) HTMSP_PB(8, 4, 16) HTMSP_PB(16, 1, 16) HTMSP_PB(16, 2, 16)
+  HTMSP_PB(16, 4, 16)
 #undef HTMSP_PB
   return nullptr;
 }

@@ -81,6 +81,29 @@ size_t persistent_local_exchange_bytes(uint32_t C);
 
 // Waves per workgroup of the one-column-group-per-wave kernel.
 constexpr uint32_t kPersistWaves = 4;
+// Rows of 64 synapses per wave for the column-group-per-wave kernels (the
+// global, local and boosted steps): the fewest of 4, 8 or 16 (at least
+// `rpc`, whole columns) that keep the grid to half the CUs, else to all of
+// them; 0 if none fits.  *grid gets the workgroups.  Fewer, fuller
+// workgroups mean fewer readers of the per-frame exchange against more
+// work per wave; measured at 960x540, 1024 x 256: 128 workgroups of 2
+// columns per wave ran 2 % (global) and 13 % (local) faster than 256 of 1,
+// and 64 of 4 ran 25 % slower.
+inline uint32_t persistent_wave_rows(uint32_t C, uint32_t rpc, int cus, uint32_t* grid) {
+  const uint32_t limits[2] = {(uint32_t)cus / 2, (uint32_t)cus};
+  for (uint32_t limit : limits) {
+    for (uint32_t rw = 4; rw <= 16; rw *= 2) {
+      if (rw < rpc) continue;
+      const uint32_t cols = rw / rpc * kPersistWaves;
+      const uint32_t g = (C + cols - 1) / cols;
+      if (g <= limit) {
+        *grid = g;
+        return rw;
+      }
+    }
+  }
+  return 0;
+}
 // The one-column-group-per-wave instance for `rpc` rows per column, `nv`
 // exchange words per lane and `rw` rows per wave; nullptr otherwise.
 const void* persistent_wave_kernel(uint32_t rpc, uint32_t nv, uint32_t rw);
@@ -159,9 +182,9 @@ struct BoostArgs {
 // Largest C of the persistent boosted step (every wave keeps every column's
 // duty cycles and boost in registers).
 constexpr uint32_t kBoostPersistMaxColumns = 1024;
-// The persistent boosted instance for `rpc` rows per column and `nv`
-// exchange words per lane (rows per wave max(4, rpc)); nullptr otherwise.
-const void* persistent_boost_kernel(uint32_t rpc, uint32_t nv);
+// The persistent boosted instance for `rpc` rows per column, `nv` exchange
+// words per lane and `rw` rows per wave; nullptr otherwise.
+const void* persistent_boost_kernel(uint32_t rpc, uint32_t nv, uint32_t rw);
 
 // Local inhibition (sp_local.hip): active [F][C] from overlaps [F][C].
 hipError_t launch_inhibit_local(const int32_t* ov, uint32_t F, uint32_t C, uint32_t grid_w,

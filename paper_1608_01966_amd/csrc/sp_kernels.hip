@@ -969,13 +969,12 @@ const void* persistent_wave_kernel(uint32_t rpc, uint32_t nv, uint32_t rw) {
 #define HTMSP_PW(P, V, R)                              \
   if (rpc == P && nv == V && rw == R)                  \
     return reinterpret_cast<const void*>(&k_sp_persistent_w<P, V, R>);
-  // The shapes a 256-CU device reaches with one workgroup per CU: C <= 256 *
-  // 4 * rw / rpc columns, nv covering C.
-  HTMSP_PW(1, 1, 4) HTMSP_PW(1, 2, 4) HTMSP_PW(1, 4, 4) HTMSP_PW(1, 8, 4) HTMSP_PW(1, 16, 4)
-  HTMSP_PW(2, 1, 4) HTMSP_PW(2, 2, 4) HTMSP_PW(2, 4, 4) HTMSP_PW(2, 8, 4) HTMSP_PW(2, 16, 8)
-  HTMSP_PW(4, 1, 4) HTMSP_PW(4, 2, 4) HTMSP_PW(4, 4, 4) HTMSP_PW(4, 8, 8) HTMSP_PW(4, 16, 16)
-  HTMSP_PW(8, 1, 8) HTMSP_PW(8, 2, 8) HTMSP_PW(8, 4, 8) HTMSP_PW(8, 8, 16)
-  HTMSP_PW(16, 1, 16) HTMSP_PW(16, 2, 16) HTMSP_PW(16, 4, 16)
+  // The shapes persistent_wave_rows gives on a 256-CU device.
+  HTMSP_PW(1, 1, 4) HTMSP_PW(1, 2, 4) HTMSP_PW(1, 4, 4) HTMSP_PW(1, 8, 4) HTMSP_PW(1, 16, 8)
+  HTMSP_PW(2, 1, 4) HTMSP_PW(2, 2, 4) HTMSP_PW(2, 4, 4) HTMSP_PW(2, 8, 8) HTMSP_PW(2, 16, 16)
+  HTMSP_PW(4, 1, 4) HTMSP_PW(4, 2, 4) HTMSP_PW(4, 4, 8) HTMSP_PW(4, 8, 16) HTMSP_PW(4, 16, 16)
+  HTMSP_PW(8, 1, 8) HTMSP_PW(8, 2, 8) HTMSP_PW(8, 4, 16) HTMSP_PW(8, 8, 16) HTMSP_PW(16, 1, 16)
+  HTMSP_PW(16, 2, 16) HTMSP_PW(16, 4, 16)
 #undef HTMSP_PW
   return nullptr;
 }

@@ -314,12 +314,12 @@ const void* persistent_local_kernel(uint32_t rpc, uint32_t nv, uint32_t rw) {
 #define HTMSP_PL(P, V, R)                              \
   if (rpc == P && nv == V && rw == R)                  \
     return reinterpret_cast<const void*>(&k_sp_persistent_local<P, V, R>);
-  // The shapes a 256-CU device reaches with one workgroup per CU.
-  HTMSP_PL(1, 1, 4) HTMSP_PL(1, 2, 4) HTMSP_PL(1, 4, 4) HTMSP_PL(1, 8, 4) HTMSP_PL(1, 16, 4)
-  HTMSP_PL(2, 1, 4) HTMSP_PL(2, 2, 4) HTMSP_PL(2, 4, 4) HTMSP_PL(2, 8, 4) HTMSP_PL(2, 16, 8)
-  HTMSP_PL(4, 1, 4) HTMSP_PL(4, 2, 4) HTMSP_PL(4, 4, 4) HTMSP_PL(4, 8, 8) HTMSP_PL(4, 16, 16)
-  HTMSP_PL(8, 1, 8) HTMSP_PL(8, 2, 8) HTMSP_PL(8, 4, 8) HTMSP_PL(8, 8, 16)
-  HTMSP_PL(16, 1, 16) HTMSP_PL(16, 2, 16) HTMSP_PL(16, 4, 16)
+  // The shapes persistent_wave_rows gives on a 256-CU device.
+  HTMSP_PL(1, 1, 4) HTMSP_PL(1, 2, 4) HTMSP_PL(1, 4, 4) HTMSP_PL(1, 8, 4) HTMSP_PL(1, 16, 8)
+  HTMSP_PL(2, 1, 4) HTMSP_PL(2, 2, 4) HTMSP_PL(2, 4, 4) HTMSP_PL(2, 8, 8) HTMSP_PL(2, 16, 16)
+  HTMSP_PL(4, 1, 4) HTMSP_PL(4, 2, 4) HTMSP_PL(4, 4, 8) HTMSP_PL(4, 8, 16) HTMSP_PL(4, 16, 16)
+  HTMSP_PL(8, 1, 8) HTMSP_PL(8, 2, 8) HTMSP_PL(8, 4, 16) HTMSP_PL(8, 8, 16) HTMSP_PL(16, 1, 16)
+  HTMSP_PL(16, 2, 16) HTMSP_PL(16, 4, 16)
 #undef HTMSP_PL
   return nullptr;
 }

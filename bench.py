@@ -456,6 +456,11 @@ def bench_local(args, torch, sp, synth):
     n_act = int(act.sum().item())
     abytes = F * (frame_bytes(cfg) + 8 * C * S + 4 * C + C) + 12 * S * n_act
     achieved = abytes / (call_ms * 1e-3) / 1e9
+    kname = pool.local_kernel
+    traffic, traffic_bytes = (None, None)
+    if kname != "plain" and F == 1000:
+        traffic, traffic_bytes = measured_traffic(f"{kname}_960x540_1024c_256s_radius80.md",
+                                                  kname, call_ms)
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -480,11 +485,11 @@ def bench_local(args, torch, sp, synth):
                                f"per neighbourhood, {F} sequential learning frames per step",
                    "frames_per_step": F, "active_per_frame": n_act / F, "path": "local"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": (pool.local_kernel if pool.local_kernel != "plain" else
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": (kname if kname != "plain" else
                                 "k_overlap_plain + k_inhibit_local + k_learn_active"),
                      "kernel_ms_per_launch": call_ms, "algorithmic_bytes_per_launch": abytes,
-                     "counter_bytes_per_launch": None},
+                     "counter_bytes_per_launch": traffic_bytes},
         "cpu_baseline": cpu,
     }
 
@@ -522,6 +527,11 @@ def bench_boost(args, torch, sp, synth):
     fps = args.steps * F / wall_s
     abytes = algorithmic_bytes_learn(cfg, win.cpu().numpy()) + F * 12 * C
     achieved = abytes / (call_ms * 1e-3) / 1e9
+    kname = pool.boost_kernel
+    traffic, traffic_bytes = (None, None)
+    if kname != "plain" and F == 1000:
+        traffic, traffic_bytes = measured_traffic(f"{kname}_960x540_1024c_256s.md", kname,
+                                                  call_ms)
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -547,11 +557,11 @@ def bench_boost(args, torch, sp, synth):
                                f"{F} sequential learning frames per step",
                    "frames_per_step": F, "path": "boost"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": (pool.boost_kernel if pool.boost_kernel != "plain" else
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": (kname if kname != "plain" else
                                 "k_overlap_plain + k_topk_plain + k_learn_plain + k_boost_update"),
                      "kernel_ms_per_launch": call_ms, "algorithmic_bytes_per_launch": abytes,
-                     "counter_bytes_per_launch": None},
+                     "counter_bytes_per_launch": traffic_bytes},
         "cpu_baseline": cpu,
     }
 
@@ -620,7 +630,7 @@ def main() -> int:
     ap.add_argument("--workload",
                     choices=["learn", "infer", "multi", "serve", "encode", "local", "boost"],
                     default="learn")
-    ap.add_argument("--local-frames", type=int, default=200)
+    ap.add_argument("--local-frames", type=int, default=1000)
     ap.add_argument("--encode-frames", type=int, default=256)
     ap.add_argument("--encode-factor", type=int, default=1)
     ap.add_argument("--streams", type=int, default=256)

@@ -293,6 +293,15 @@ int sp_step_local_kernel(const sp_handle* h);
  * handle. */
 int sp_step_boost_kernel(const sp_handle* h);
 
+/* For tests of the failure path (callers: test suites, not applications):
+ * the next persistent launch of sp_step, sp_step_local or sp_step_boost on
+ * this handle waits for exchange entries that are never written, giving up
+ * after `spin_limit` polls (1..2^21) as a stalled exchange would, so that
+ * every wave leaves its loop and the launch drains; sp_sync then reports
+ * SP_EDEVICE and the handle is broken.  Applies to one launch; a plain
+ * (non-persistent) step ignores it.  SP_EINVAL on a bad handle or limit. */
+int sp_test_stall(sp_handle* h, uint32_t spin_limit);
+
 /* Synchronises `stream` and reports a device-side failure of an earlier
  * step on this handle (SP_EDEVICE, after which the handle is SP_EBROKEN). */
 int sp_sync(sp_handle* h, void* stream);

@@ -28,7 +28,8 @@ __all__ = [
     "sp_workspace_bytes", "sp_check_state_host", "sp_create", "sp_check_state", "sp_step",
     "sp_step_plain", "sp_infer", "sp_step_many", "sp_set_histogram", "sp_encode",
     "sp_inhibit_local", "sp_step_local", "sp_step_boost", "sp_boost_state", "sp_boost_reset",
-    "sp_encoded_bits", "sp_step_is_persistent", "sp_step_kernel", "sp_step_local_kernel", "sp_step_boost_kernel", "STEP_KERNELS",
+    "sp_encoded_bits", "sp_step_is_persistent", "sp_step_kernel", "sp_step_local_kernel",
+    "sp_step_boost_kernel", "sp_test_stall", "STEP_KERNELS",
     "sp_sync",
     "sp_destroy",
     "sp_last_error", "SP_OK", "SP_EINVAL", "SP_ENOMEM", "SP_EDEVICE", "SP_EBROKEN",
@@ -302,6 +303,12 @@ def sp_step_boost_kernel(h: int) -> str:
     """The execution sp_step_boost uses: "plain" or "k_sp_persistent_boost"."""
     code = _check(lib().sp_step_boost_kernel(ctypes.c_void_p(h)), "sp_step_boost_kernel")
     return "k_sp_persistent_boost" if code == 2 else "plain"
+
+
+def sp_test_stall(h: int, spin_limit: int) -> None:
+    """Failure-path tests only: the next persistent launch on this handle
+    stalls on its exchange and gives up after `spin_limit` polls."""
+    _check(lib().sp_test_stall(ctypes.c_void_p(h), spin_limit), "sp_test_stall")
 
 
 def sp_sync(h: int, stream=None) -> None:

@@ -83,6 +83,7 @@ SIGNATURES = [
     ("sp_step_kernel", ctypes.c_int, [P]),
     ("sp_step_local_kernel", ctypes.c_int, [P]),
     ("sp_step_boost_kernel", ctypes.c_int, [P]),
+    ("sp_test_stall", ctypes.c_int, [P, ctypes.c_uint32]),
     ("sp_sync", ctypes.c_int, [P, P]),
     ("sp_destroy", ctypes.c_int, [P]),
     ("sp_last_error", ctypes.c_char_p, []),

@@ -48,6 +48,9 @@ struct sp_handle {
   uint32_t lgrid;
   const void* bkernel;  // persistent boosted step (null: per-frame launches)
   uint32_t bgrid;
+  // sp_test_stall: the next persistent launch waits for entries that are
+  // never written, with this spin limit (0: off)
+  uint32_t stall_spins;
   uint64_t* xloc;
   uint64_t xloc_frames;
   bool broken;
@@ -556,7 +559,9 @@ int sp_step(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames, int l
   a.learn = learn ? 1u : 0u;
   a.frame_base = (uint32_t)h->xchg_frames;
   a.replicas = h->replicas;
-  a.spin_limit = kSpinLimit;
+  a.spin_limit = h->stall_spins ? h->stall_spins : kSpinLimit;
+  a.stall = h->stall_spins ? 1u : 0u;
+  h->stall_spins = 0;
   a.sh = h->sh;
   void* args[] = {&a};
   hipError_t e = hipLaunchCooperativeKernel(h->pkernel, dim3(h->grid), dim3(h->block), args,
@@ -787,7 +792,9 @@ int sp_step_local(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames,
     a.learn = learn ? 1u : 0u;
     a.frame_base = (uint32_t)h->xloc_frames;
     a.replicas = htmsp::kPersistReplicas;
-    a.spin_limit = kSpinLimit;
+    a.spin_limit = h->stall_spins ? h->stall_spins : kSpinLimit;
+    a.stall = h->stall_spins ? 1u : 0u;
+    h->stall_spins = 0;
     a.grid_w = grid_w;
     a.radius = radius;
     a.sh = sh;
@@ -883,7 +890,9 @@ int sp_step_boost(sp_handle* h, const sp_boost_config* bc, const uint32_t* frame
     a.learn = learn ? 1u : 0u;
     a.frame_base = (uint32_t)h->xloc_frames;
     a.replicas = htmsp::kPersistReplicas;
-    a.spin_limit = kSpinLimit;
+    a.spin_limit = h->stall_spins ? h->stall_spins : kSpinLimit;
+    a.stall = h->stall_spins ? 1u : 0u;
+    h->stall_spins = 0;
     a.b = bp;
     a.sh = sh;
     void* args[] = {&a};
@@ -974,6 +983,15 @@ int sp_set_histogram(sp_handle* h, uint32_t* hist_dev) {
 int sp_step_is_persistent(const sp_handle* h) {
   if (!h) return fail(SP_EINVAL, "handle is NULL");
   return h->persistent ? 1 : 0;
+}
+
+int sp_test_stall(sp_handle* h, uint32_t spin_limit) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (spin_limit < 1 || spin_limit > kSpinLimit)
+    return fail(SP_EINVAL, "spin_limit=%u outside 1..%u", spin_limit, kSpinLimit);
+  h->stall_spins = spin_limit;
+  return ok();
 }
 
 int sp_step_boost_kernel(const sp_handle* h) {

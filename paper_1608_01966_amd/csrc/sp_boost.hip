@@ -265,7 +265,8 @@ __global__ __launch_bounds__(kPersistWaves * kWave) void k_sp_persistent_boost(B
       if constexpr (POLL) {
 #pragma unroll
         for (int u = 0; u < NV; ++u) v[u] = load_entries(xs + u * kWave + lane);
-        const uint64_t tagw = (uint64_t)tg * kOnes16;
+        // (a.stall != 0 only in tests of the failure path)
+        const uint64_t tagw = (uint64_t)((((g + 1u + a.stall) & 3u) << kTagShift)) * kOnes16;
         uint32_t spins = 0;
         while (true) {
           bool ok = true;

@@ -29,6 +29,7 @@ struct PersistArgs {
   uint32_t* xchg;     // [replicas][2][arrays][entries] 16-bit tagged overlaps
   uint32_t* err;      // set to non-zero when a wave gives up waiting
   uint32_t F, learn, frame_base, replicas, spin_limit;  // frame_base counts exchanges
+  uint32_t stall;  // 0; a test of the failure path sets 1 (see sp_test_stall)
   Shape sh;
 };
 
@@ -69,6 +70,7 @@ struct LocalArgs {
   uint64_t* xchg;      // [replicas][2][entries / 4] tagged overlaps
   uint32_t* err;
   uint32_t F, learn, frame_base, replicas, spin_limit;
+  uint32_t stall;  // 0; a test of the failure path sets 1 (see sp_test_stall)
   uint32_t grid_w, radius;  // the neighbourhood; n = sh.k
   Shape sh;
 };
@@ -176,6 +178,7 @@ struct BoostArgs {
   uint32_t* odc;     // [C] overlap duty cycles
   uint32_t* boost;   // [C] boosts (1/256)
   uint32_t F, learn, frame_base, replicas, spin_limit;
+  uint32_t stall;  // 0; a test of the failure path sets 1 (see sp_test_stall)
   BoostParams b;
   Shape sh;
 };

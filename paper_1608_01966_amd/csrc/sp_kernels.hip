@@ -440,7 +440,9 @@ __global__ __launch_bounds__(128) void k_sp_persistent(PersistArgs a) {
     // The previous pair's outputs, and the next pair's speculation, before
     // the first read of the exchange: entries are rarely all in before then,
     // and a read that comes back stale costs a whole further round trip.
-    const uint64_t tagw = (uint64_t)tg * kOnes16;
+    // the tag readers wait for (a.stall != 0 only in tests of the failure
+    // path: a tag that is never written into this slot)
+    const uint64_t tagw = (uint64_t)((((g + 1u + a.stall) & 3u) << kTagShift)) * kOnes16;
     const uint64_t* xs = x64 + (size_t)(rep * 2 + slot) * NARR * (CPAD / 4);
     uint64_t v0[NV], vL[NV], vW[NV];
     if (t > 0) {
@@ -784,7 +786,8 @@ __global__ __launch_bounds__(kPersistWaves * kWave) void k_sp_persistent_w(Persi
           vL[u] = load_entries(xs + CPAD / 4 + u * kWave + lane);
           vW[u] = load_entries(xs + 2 * (CPAD / 4) + u * kWave + lane);
         }
-        const uint64_t tagw = (uint64_t)tg * kOnes16;
+        // (a.stall != 0 only in tests of the failure path)
+        const uint64_t tagw = (uint64_t)((((g + 1u + a.stall) & 3u) << kTagShift)) * kOnes16;
         uint32_t spins = 0;
         while (true) {
           bool ok = true;

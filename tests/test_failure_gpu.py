@@ -1,0 +1,68 @@
+"""The persistent steps' failure path, forced from the host: sp_test_stall
+makes the next persistent launch wait for exchange entries that are never
+written, under a small spin limit.  Every wave must give up within its own
+bounded wait and the launch must drain; sp_sync then reports SP_EDEVICE, the
+handle refuses further steps (SP_EBROKEN) and can still be destroyed."""
+import numpy as np
+import pytest
+
+import paper_1608_01966_amd as sp
+from paper_1608_01966_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+BC = {"period_log2": 6, "min_pct_q16": 16384, "max_boost_q8": 2560, "bump_q8": 13}
+
+
+def _step(kind, pool, cfg, frames, F):
+    import torch
+    C, k = cfg["num_columns"], cfg["winners"]
+    if kind == "global":
+        sp.sp_step(pool.handle, cfg, frames, True, None,
+                   torch.empty((F, k), dtype=torch.int32, device="cuda"))
+    elif kind == "local":
+        sp.sp_step_local(pool.handle, cfg, frames, True, 1024, 80, None,
+                         torch.empty((F, C), dtype=torch.uint8, device="cuda"))
+    else:
+        sp.sp_step_boost(pool.handle, cfg, BC, frames, True, None,
+                         torch.empty((F, k), dtype=torch.int32, device="cuda"))
+
+
+@pytest.mark.parametrize("kind", ["global", "local", "boost"])
+def test_stalled_exchange_drains_and_reports(kind):
+    import torch
+    w = synth.workload_paper_scale(frames=8, columns=1024, synapses=256)
+    cfg = w.cfg
+    pool = sp.SpatialPooler(cfg, w.idx, w.perm)
+    assert {"global": pool.kernel, "local": pool.local_kernel,
+            "boost": pool.boost_kernel}[kind] != "plain"
+    frames = torch.from_numpy(w.frames.view(np.int32)).cuda()
+    sp.sp_test_stall(pool.handle, 200)
+    _step(kind, pool, cfg, frames, 8)
+    with pytest.raises(sp.SpError) as e:
+        pool.sync()
+    assert e.value.code == sp.SP_EDEVICE
+    with pytest.raises(sp.SpError) as e:
+        _step(kind, pool, cfg, frames, 8)
+    assert e.value.code == sp.SP_EBROKEN
+    pool.close()
+
+
+def test_stall_applies_to_one_launch_only():
+    """A stall request is consumed by one launch: a fresh handle that never
+    had one runs the same frames to the same results as before."""
+    import torch
+    w = synth.workload_paper_scale(frames=6, columns=1024, synapses=256)
+    cfg = w.cfg
+    frames = torch.from_numpy(w.frames.view(np.int32)).cuda()
+    a = sp.SpatialPooler(cfg, w.idx, w.perm)
+    with pytest.raises(sp.SpError):
+        sp.sp_test_stall(a.handle, 0)
+    ov, win = a.step(frames)
+    a.sync()
+    b = sp.SpatialPooler(cfg, w.idx, w.perm)
+    ov2, win2 = b.step(frames)
+    b.sync()
+    assert torch.equal(win, win2) and torch.equal(ov, ov2)
+    a.close()
+    b.close()

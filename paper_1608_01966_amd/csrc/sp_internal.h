@@ -38,9 +38,12 @@ constexpr uint32_t kPersistMaxColumns = 4096;
 // Largest S it holds: 16 rows of 64 synapses per workgroup.
 constexpr uint32_t kPersistMaxSynapses = 1024;
 // Exchange copies the workspace holds (one per XCD at most), and the number
-// used: readers pick the copy of their XCD modulo this.
+// used: readers pick the copy of their XCD modulo this.  Measured at
+// 960x540, 1024 x 256 with the column-group-per-wave kernels: one copy is
+// 2-3 % faster than two and two than four (every copy costs each publisher
+// a store; the readers of one copy do not contend measurably).
 constexpr uint32_t kPersistMaxReplicas = 8;
-constexpr uint32_t kPersistReplicas = 2;
+constexpr uint32_t kPersistReplicas = 1;
 
 // LDS of one persistent workgroup holding `rows` rows of 64 synapses.
 size_t persistent_lds_bytes(uint32_t rows);

@@ -272,13 +272,11 @@ int sp_set_histogram(sp_handle* h, uint32_t* hist_dev);
 int sp_step_is_persistent(const sp_handle* h);
 
 /* Which execution sp_step uses for this handle's shape on its device:
- * SP_KERNEL_PLAIN (three launches a frame), SP_KERNEL_PERSISTENT_GROUP (one
- * persistent launch, 16 rows of 64 synapses per workgroup) or
- * SP_KERNEL_PERSISTENT_WAVE (one persistent launch, a column group per wave,
- * one workgroup per CU); negative on a bad handle.  Informational: every
- * execution gives the same results. */
+ * SP_KERNEL_PLAIN (three launches a frame) or SP_KERNEL_PERSISTENT_WAVE (one
+ * persistent launch, a column group per wave, one workgroup per CU);
+ * negative on a bad handle.  Informational: every execution gives the same
+ * results. */
 #define SP_KERNEL_PLAIN 0
-#define SP_KERNEL_PERSISTENT_GROUP 1
 #define SP_KERNEL_PERSISTENT_WAVE 2
 int sp_step_kernel(const sp_handle* h);
 

@@ -285,7 +285,7 @@ def sp_step_is_persistent(h: int) -> bool:
 
 
 # sp_step_kernel codes, and the HIP kernel each one runs.
-STEP_KERNELS = {0: "plain", 1: "k_sp_persistent", 2: "k_sp_persistent_w"}
+STEP_KERNELS = {0: "plain", 2: "k_sp_persistent_w"}
 
 
 def sp_step_kernel(h: int) -> str:

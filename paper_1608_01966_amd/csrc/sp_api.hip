@@ -40,8 +40,6 @@ struct sp_handle {
   bool persistent;
   uint32_t grid, block, replicas;
   const void* pkernel;
-  size_t plds;
-  int pkind;  // SP_KERNEL_* of the persistent instance
   // persistent local-inhibition step: instance (null: per-frame launches),
   // grid, its exchange and the count of exchanges it has used
   const void* lkernel;
@@ -198,10 +196,10 @@ uint32_t next_pow2(uint32_t x) {
   return p;
 }
 
-// Chooses the persistent kernel instance: rows of 64 synapses per column
-// rounded up to a power of two and exchange words per lane for C; the
-// one-column-group-per-wave kernel when its grid fits one workgroup per CU,
-// else the 16-rows-per-workgroup kernel; the grid must be co-resident.
+// Chooses the persistent kernel instances of the global, local and boosted
+// steps: rows of 64 synapses per column rounded up to a power of two,
+// exchange words per lane for C, rows per wave by persistent_wave_rows; the
+// grid must be co-resident.  Shapes without an instance run the plain path.
 void plan_persistent(sp_handle* h) {
   h->persistent = false;
   h->lkernel = nullptr;
@@ -242,8 +240,7 @@ void plan_persistent(sp_handle* h) {
       h->lgrid = wgrid;
     }
   }
-  // The global step: the column-group-per-wave kernel where its split fits,
-  // else 16 rows per workgroup.
+  // The global step.
   if (rw) {
     const void* kw = htmsp::persistent_wave_kernel(rpc, nv, rw);
     if (fits(kw)) {
@@ -251,28 +248,9 @@ void plan_persistent(sp_handle* h) {
       h->block = htmsp::kPersistWaves * 64;
       h->replicas = htmsp::kPersistReplicas;
       h->pkernel = kw;
-      h->plds = 0;
-      h->pkind = SP_KERNEL_PERSISTENT_WAVE;
       h->persistent = true;
-      return;
     }
   }
-  const uint32_t rows = htmsp::kPersistRows;
-  const void* k = htmsp::persistent_kernel(rpc, nv, rows);
-  if (!k) return;
-  const uint32_t cpw = rows / rpc;
-  const uint32_t grid = (sh.C + cpw - 1) / cpw;
-  const size_t lds = htmsp::persistent_lds_bytes(rows);
-  int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 128, lds) != hipSuccess) return;
-  if ((uint64_t)per_cu * (uint64_t)cus < grid) return;
-  h->grid = grid;
-  h->block = 128;
-  h->replicas = htmsp::kPersistReplicas;
-  h->pkernel = k;
-  h->plds = lds;
-  h->pkind = SP_KERNEL_PERSISTENT_GROUP;
-  h->persistent = true;
 }
 
 int run_check_state(sp_handle* h, hipStream_t s) {
@@ -564,8 +542,7 @@ int sp_step(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames, int l
   h->stall_spins = 0;
   a.sh = h->sh;
   void* args[] = {&a};
-  hipError_t e = hipLaunchCooperativeKernel(h->pkernel, dim3(h->grid), dim3(h->block), args,
-                                            (unsigned int)h->plds,
+  hipError_t e = hipLaunchCooperativeKernel(h->pkernel, dim3(h->grid), dim3(h->block), args, 0,
                                             static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "persistent step launch");
   h->xchg_frames += (num_frames + 1) / 2;
@@ -1006,8 +983,7 @@ int sp_step_local_kernel(const sp_handle* h) {
 
 int sp_step_kernel(const sp_handle* h) {
   if (!h) return fail(SP_EINVAL, "handle is NULL");
-  if (!h->persistent) return SP_KERNEL_PLAIN;
-  return h->pkind;
+  return h->persistent ? SP_KERNEL_PERSISTENT_WAVE : SP_KERNEL_PLAIN;
 }
 
 int sp_sync(sp_handle* h, void* stream) {

@@ -17,9 +17,8 @@ struct Shape {
   uint32_t theta, inc, dec; // connected threshold, increment, decrement (x256)
 };
 
-// Persistent multi-frame step (both instances): every column spread over
-// `rpc` rows of 64 synapses, groups of consecutive columns per wave or per
-// workgroup.
+// Persistent multi-frame step: every column spread over `rpc` rows of 64
+// synapses, a group of consecutive columns per wave.
 struct PersistArgs {
   const uint32_t* idx;
   float* perm;
@@ -45,23 +44,11 @@ constexpr uint32_t kPersistMaxSynapses = 1024;
 constexpr uint32_t kPersistMaxReplicas = 8;
 constexpr uint32_t kPersistReplicas = 1;
 
-// LDS of one persistent workgroup holding `rows` rows of 64 synapses.
-size_t persistent_lds_bytes(uint32_t rows);
-// Rows of 64 synapses per workgroup of the 16-row instance (a main and a
-// producer wave), used where the column-group-per-wave instance's grid does
-// not fit one workgroup per CU.  Within this instance, fewer rows (more
-// workgroups) multiply the readers of the per-frame exchange; measured at
-// 960x540, 1024 x 256: 4 rows (1024 workgroups) ran 2.7x slower than 16.
-constexpr uint32_t kPersistRows = 16;
 // Exchange arrays per slot (frame t, frame t+1 if lost, frame t+1 if won).
 uint32_t persistent_exchange_arrays();
 // 16-bit exchange entries per array for C columns: 256 times the power of two
 // of 64-bit words per lane that covers C.
 uint32_t persistent_exchange_entries(uint32_t C);
-// The kernel instance for `rpc` rows per column (1, 2, 4, 8 or 16), `nv`
-// 64-bit exchange words per lane (1, 2, 4, 8 or 16) and `rows` rows per
-// workgroup (kPersistRows); nullptr otherwise.
-const void* persistent_kernel(uint32_t rpc, uint32_t nv, uint32_t rows);
 // Persistent learning step with local inhibition: F frames in one
 // cooperative launch, one frame per exchange of every column's overlap.
 struct LocalArgs {

@@ -10,10 +10,8 @@
 //     the next frames are gathered while the exchange is in flight;
 //     per-frame overlaps go to all other workgroups through a tagged device
 //     buffer, and the global top-k is resolved redundantly so that every
-//     wave knows which of its own columns learn, with no second exchange.
-//     Two instances: a column group per wave (k_sp_persistent_w, one
-//     workgroup per CU) and 16 rows per workgroup (k_sp_persistent, for
-//     grids larger than that).
+//     wave knows which of its own columns learn, with no second exchange
+//     (k_sp_persistent_w: a column group per wave, one workgroup per CU).
 // Permanences are handled as integers q = 256 * permanence (0..256), so
 // every comparison and update is exact.
 #include "sp_device.h"
@@ -170,35 +168,14 @@ __global__ __launch_bounds__(256) void k_learn_plain(const uint32_t* __restrict_
 // ---------------------------------------------------------------------------
 // Persistent multi-frame step.
 //
-// Workgroup g (two waves) owns CPW = ROWS / RPC consecutive columns from
-// g*CPW; row r holds synapses (r % RPC)*64 + lane of local column r / RPC.
-// ROWS is 16 (see kPersistRows).
-//   wave 0 (main) keeps the synapse state in registers for the whole launch
-//     (idx << 9 | q, plus the mask of the input bit when connected) and, per
-//     frame: overlap of its columns, publish, collect every column's
-//     overlap, resolve the global top-k, learn on its winning columns, and
-//     write the previous frame's outputs while the exchange is in flight.
-//   wave 1 (producer) gathers the input words the group's synapses need, up
-//     to kRing - 1 frames ahead, into an LDS ring, so that no gather latency
-//     sits in front of the main wave's exchange loads.
 // Exchange: one 16-bit entry [tag:2 | overlap:14] per column, written as
-// whole words with agent-scope stores into each of `replicas` copies and read with
-// agent-scope 64-bit loads (four columns each) from the copy of the reader's
-// XCD, so that readers spread over several memory channels.  Frame g of the
-// handle uses slot g & 1 and tag (g + 1) & 3; the slot's previous content
-// belongs to frame g - 2 with tag (g - 1) & 3 (or is the zeroed initial
-// state), so a stale entry is never taken for a fresh one, and a slot is
-// rewritten only after every workgroup has finished reading it.
-constexpr uint32_t kRing = 8;
-
-__device__ __forceinline__ void store_entry(uint16_t* p, uint16_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ void store_half(uint32_t* p, uint32_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
+// whole 64-bit words (four columns) with agent-scope stores into each of
+// `replicas` copies and read with agent-scope 64-bit loads from the copy of
+// the reader's XCD.  Exchange g of the handle uses slot g & 1 and tag
+// (g + 1) & 3; the slot's previous content belongs to exchange g - 2 with tag
+// (g - 1) & 3 (or is the zeroed initial state), so a stale entry is never
+// taken for a fresh one, and a slot is rewritten only after every workgroup
+// has finished reading it.
 
 // Whether this lane's own column (overlap v, lane < ncols) wins: above T, or
 // equal to T and among the first `need` such columns in column order.
@@ -245,364 +222,14 @@ __device__ __forceinline__ void write_frame(const PersistArgs& a, const uint64_t
 
 // Persistent multi-frame step, two frames per exchange.  Learning makes
 // frame t + 1 depend on which columns win frame t, but only through the
-// winners' own synapses; so each group publishes, with its frame-t
-// overlaps, the frame-(t+1) overlaps its columns will have if they lose
-// frame t and if they win it.  Every group resolves frame t's winners,
-// picks each column's frame-(t+1) overlap accordingly and resolves frame
-// t + 1 as well, so one exchange round trip serves two frames; the results
-// are exactly those of stepping the frames one by one.
-template <int RPC, int NV, int ROWS>
-__global__ __launch_bounds__(128) void k_sp_persistent(PersistArgs a) {
-  constexpr uint32_t CPW = ROWS / RPC;
-  constexpr uint32_t CPAD = NV * 4 * kWave;  // entries per exchange array
-  constexpr uint32_t NARR = 3;               // frame t, frame t+1 if lost, if won
-  extern __shared__ uint32_t lds[];
-  uint32_t* ring = lds;                         // [kRing][ROWS][64] input words
-  uint32_t* ctl = lds + kRing * ROWS * kWave;  // [0] produced, [1] consumed, [2] abort
-  const Shape sh = a.sh;
-  const uint32_t lane = threadIdx.x % kWave;
-  const uint32_t c_begin = blockIdx.x * CPW;
-  const uint32_t ncols = min(CPW, sh.C - c_begin);
-
-  if (threadIdx.x == 0) {
-    ctl[0] = 0;
-    ctl[1] = 0;
-    ctl[2] = 0;
-  }
-  __syncthreads();
-
-  if (threadIdx.x >= kWave) {
-    // ---- producer wave ----
-    uint32_t wi[ROWS];
-#pragma unroll
-    for (uint32_t r = 0; r < ROWS; ++r) {
-      const uint32_t j = r / RPC, s = (r % RPC) * kWave + lane;
-      const bool ok = j < ncols && s < sh.S;
-      const size_t off = ok ? (size_t)(c_begin + j) * sh.S + s : 0;
-      wi[r] = ok ? min(a.idx[off], sh.N - 1) >> 5 : 0u;
-    }
-    for (uint32_t t = 0; t < a.F; ++t) {
-      uint32_t spins = 0;
-      while (lds_acquire(&ctl[1]) + kRing <= t) {
-        if (lds_acquire(&ctl[2]) != 0 || ++spins > a.spin_limit) {
-          lds_release(&ctl[2], 1u);
-          return;
-        }
-        __builtin_amdgcn_s_sleep(2);
-      }
-      const uint32_t* fr = a.frames + (size_t)t * sh.W;
-      uint32_t w[ROWS];
-#pragma unroll
-      for (uint32_t r = 0; r < ROWS; ++r) w[r] = fr[wi[r]];
-      uint32_t* dst = ring + (t % kRing) * ROWS * kWave + lane;
-#pragma unroll
-      for (uint32_t r = 0; r < ROWS; ++r) dst[r * kWave] = w[r];
-      lds_release(&ctl[0], t + 1);
-    }
-    return;
-  }
-
-  // ---- main wave ----
-  uint32_t st[ROWS], msk[ROWS];
-#pragma unroll
-  for (uint32_t r = 0; r < ROWS; ++r) {
-    const uint32_t j = r / RPC, s = (r % RPC) * kWave + lane;
-    const bool ok = j < ncols && s < sh.S;
-    const size_t off = ok ? (size_t)(c_begin + j) * sh.S + s : 0;
-    const uint32_t i = min(a.idx[off], sh.N - 1);
-    const uint32_t q = perm_to_q(a.perm[off]);
-    st[r] = ok ? (i << 9) | q : 0u;
-    msk[r] = (ok && q >= sh.theta) ? (1u << (i & 31u)) : 0u;
-  }
-  // Rows that hold a synapse in this lane.
-  uint32_t row_ok = 0;
-#pragma unroll
-  for (uint32_t r = 0; r < ROWS; ++r)
-    row_ok |= ((r / RPC) < ncols && (r % RPC) * kWave + lane < sh.S) ? 1u << r : 0u;
-
-  uint16_t* x16 = reinterpret_cast<uint16_t*>(a.xchg);
-  uint32_t* x32w = a.xchg;
-  uint64_t* x64w = reinterpret_cast<uint64_t*>(a.xchg);
-  const uint64_t* x64 = x64w;
-  const uint32_t rep = xcc_id() % a.replicas;
-  const bool mine = lane < ncols;
-
-  uint64_t ev0[NV], ev1[NV];  // overlaps of the pair's two frames, tags stripped
-#pragma unroll
-  for (int u = 0; u < NV; ++u) {
-    ev0[u] = 0;
-    ev1[u] = 0;
-  }
-  uint32_t guess = 1 + sh.S / 16;
-  FrameResult r0 = {0, 0, 0, 0, false}, r1 = {0, 0, 0, 0, false};
-  bool abort = false;
-
-  // Publishes the group's CPW entries of exchange array `arr` as whole words
-  // (entries past C land in the padding that readers skip).
-  auto publish = [&](uint32_t slot, uint32_t arr, uint32_t tg, const uint32_t(&ovs)[CPW]) {
-    if constexpr (CPW >= 4) {
-      uint64_t word = 0;
-#pragma unroll
-      for (uint32_t q = 0; q < CPW / 4; ++q) {
-        const uint64_t wq = (uint64_t)(tg | ovs[4 * q]) | ((uint64_t)(tg | ovs[4 * q + 1]) << 16) |
-                            ((uint64_t)(tg | ovs[4 * q + 2]) << 32) |
-                            ((uint64_t)(tg | ovs[4 * q + 3]) << 48);
-        word = lane == q ? wq : word;
-      }
-      if (lane < CPW / 4)
-        for (uint32_t rr = 0; rr < a.replicas; ++rr)
-          store_word(x64w + (((size_t)(rr * 2 + slot) * NARR + arr) * CPAD + c_begin) / 4 + lane,
-                     word);
-    } else if constexpr (CPW == 2) {
-      if (lane == 0)
-        for (uint32_t rr = 0; rr < a.replicas; ++rr)
-          store_half(x32w + (((size_t)(rr * 2 + slot) * NARR + arr) * CPAD + c_begin) / 2,
-                     (tg | ovs[0]) | ((tg | ovs[1]) << 16));
-    } else {
-      if (lane == 0)
-        for (uint32_t rr = 0; rr < a.replicas; ++rr)
-          store_entry(x16 + ((size_t)(rr * 2 + slot) * NARR + arr) * CPAD + c_begin,
-                      (uint16_t)(tg | ovs[0]));
-    }
-  };
-
-  // Input words of frames [t, t + nf) from the producer's ring.
-  auto load_pair = [&](uint32_t t, bool two, uint32_t (&x0)[ROWS], uint32_t (&x1)[ROWS]) {
-    const uint32_t nf = two ? 2u : 1u;
-    uint32_t spins = 0;
-    while (lds_acquire(&ctl[0]) < t + nf) {
-      if (lds_acquire(&ctl[2]) != 0 || ++spins > a.spin_limit) return false;
-      __builtin_amdgcn_s_sleep(1);
-    }
-    const uint32_t* s0 = ring + (t % kRing) * ROWS * kWave + lane;
-    const uint32_t* s1 = ring + ((t + 1) % kRing) * ROWS * kWave + lane;
-#pragma unroll
-    for (uint32_t r = 0; r < ROWS; ++r) {
-      x0[r] = s0[r * kWave];
-      x1[r] = two ? s1[r * kWave] : 0u;
-    }
-    lds_release(&ctl[1], t + nf);
-    return true;
-  };
-
-  // What a pair publishes, for the columns in `cols` (a mask of own columns):
-  // frame t's overlap; the state after learning frame t; frame t + 1's
-  // overlap if the column loses frame t (same state) and if it wins it.
-  auto products = [&](uint32_t cols, const uint32_t (&x0)[ROWS], const uint32_t (&x1)[ROWS],
-                      uint32_t (&o0)[CPW], uint32_t (&oL)[CPW], uint32_t (&oW)[CPW],
-                      uint32_t (&sW)[ROWS], uint32_t (&mW)[ROWS]) {
-#pragma unroll
-    for (uint32_t j = 0; j < CPW; ++j) {
-      if ((cols >> j) & 1u) {
-        uint32_t r0 = 0, rL = 0, rW = 0;
-#pragma unroll
-        for (uint32_t rr = 0; rr < RPC; ++rr) {
-          const uint32_t r = j * RPC + rr;
-          const uint32_t i = st[r] >> 9;
-          const uint32_t q = learn_q(st[r] & 511u, input_bit(x0[r], i), sh);
-          const bool ok = a.learn && ((row_ok >> r) & 1u);  // no learning: both cases agree
-          sW[r] = ok ? (i << 9) | q : st[r];
-          mW[r] = ok ? (q >= sh.theta ? 1u << (i & 31u) : 0u) : msk[r];
-          r0 += (uint32_t)__popcll(__ballot((x0[r] & msk[r]) != 0u));
-          rL += (uint32_t)__popcll(__ballot((x1[r] & msk[r]) != 0u));
-          rW += (uint32_t)__popcll(__ballot((x1[r] & mW[r]) != 0u));
-        }
-        const bool live = j < ncols;
-        o0[j] = (live && r0 >= sh.m) ? r0 : 0u;
-        oL[j] = (live && rL >= sh.m) ? rL : 0u;
-        oW[j] = (live && rW >= sh.m) ? rW : 0u;
-      }
-    }
-  };
-
-  constexpr uint32_t kAllCols = (1u << CPW) - 1u;
-  uint32_t w0[ROWS], w1[ROWS];       // the pair's input words
-  uint32_t ov0[CPW], ovL[CPW], ovW[CPW];
-  uint32_t stW[ROWS], mskW[ROWS];
-  uint32_t prev_t = 0;
-  bool prev_two = false;
-  if (a.F > 0) {
-    abort = !load_pair(0, a.F > 1, w0, w1);
-    if (!abort) products(kAllCols, w0, w1, ov0, ovL, ovW, stW, mskW);
-  }
-  for (uint32_t t = 0; t < a.F && !abort; t += 2) {
-    const bool two = t + 1 < a.F;
-
-    // Publish into every replica.
-    const uint32_t g = a.frame_base + t / 2;
-    const uint32_t tag = (g + 1u) & 3u;
-    const uint32_t slot = g & 1u;
-    const uint32_t tg = tag << kTagShift;
-    publish(slot, 0, tg, ov0);
-    publish(slot, 1, tg, ovL);
-    publish(slot, 2, tg, ovW);
-
-    // The previous pair's outputs, and the next pair's speculation, before
-    // the first read of the exchange: entries are rarely all in before then,
-    // and a read that comes back stale costs a whole further round trip.
-    // the tag readers wait for (a.stall != 0 only in tests of the failure
-    // path: a tag that is never written into this slot)
-    const uint64_t tagw = (uint64_t)((((g + 1u + a.stall) & 3u) << kTagShift)) * kOnes16;
-    const uint64_t* xs = x64 + (size_t)(rep * 2 + slot) * NARR * (CPAD / 4);
-    uint64_t v0[NV], vL[NV], vW[NV];
-    if (t > 0) {
-      write_frame(a, ev0, r0, prev_t, lane, mine, c_begin, blockIdx.x == 0);
-      if (prev_two) write_frame(a, ev1, r1, prev_t + 1, lane, mine, c_begin, blockIdx.x == 0);
-    }
-
-    // Speculation while the exchange is in flight: the next pair's products
-    // with the current state, which stays right for every own column that
-    // wins neither frame of this pair (most of them); the others are redone
-    // once this pair's winners are known.
-    const uint32_t tn = t + 2;
-    const bool has_next = tn < a.F, two_next = tn + 1 < a.F;
-    uint32_t n0[ROWS], n1[ROWS];
-    uint32_t sov0[CPW], sovL[CPW], sovW[CPW];
-    uint32_t sstW[ROWS], smskW[ROWS];
-    if (has_next) {
-      if (!load_pair(tn, two_next, n0, n1)) {
-        abort = true;
-        break;
-      }
-      products(kAllCols, n0, n1, sov0, sovL, sovW, sstW, smskW);
-    }
-
-    // Collect every column's entries from this XCD's replica.
-#pragma unroll
-    for (int u = 0; u < NV; ++u) {
-      v0[u] = load_entries(xs + u * kWave + lane);
-      vL[u] = load_entries(xs + CPAD / 4 + u * kWave + lane);
-      vW[u] = load_entries(xs + 2 * (CPAD / 4) + u * kWave + lane);
-    }
-    {
-      uint32_t spins = 0;
-      while (true) {
-        bool ok = true;
-#pragma unroll
-        for (int u = 0; u < NV; ++u) {
-          const uint64_t tm = tag_mask(u, lane, sh.C);
-          ok = ok && ((v0[u] ^ tagw) & tm) == 0ull && ((vL[u] ^ tagw) & tm) == 0ull &&
-               ((vW[u] ^ tagw) & tm) == 0ull;
-        }
-        if (__all(ok)) break;
-        if (++spins > a.spin_limit || ((spins & 63u) == 0 && load_tagged(a.err) != 0)) {
-          abort = true;
-          break;
-        }
-#pragma unroll
-        for (int u = 0; u < NV; ++u) {
-          const uint64_t tm = tag_mask(u, lane, sh.C);
-          if (((v0[u] ^ tagw) & tm) != 0ull) v0[u] = load_entries(xs + u * kWave + lane);
-          if (((vL[u] ^ tagw) & tm) != 0ull) vL[u] = load_entries(xs + CPAD / 4 + u * kWave + lane);
-          if (((vW[u] ^ tagw) & tm) != 0ull)
-            vW[u] = load_entries(xs + 2 * (CPAD / 4) + u * kWave + lane);
-        }
-      }
-    }
-    if (abort) break;
-
-    // Frame t: threshold, and which own columns win.
-    const uint32_t my0 = lane_value(ov0, lane);
-#pragma unroll
-    for (int u = 0; u < NV; ++u) ev0[u] = v0[u] & kFieldBits;
-    uint32_t c_hi;
-    const uint32_t T0 = topk_threshold(ev0, sh.S, sh.k, guess, &c_hi);
-    r0.T = T0;
-    r0.need = T0 ? sh.k - c_hi : 0u;
-    r0.nsel = T0 ? sh.k : c_hi;
-    r0.ov = my0;
-    r0.sel = own_wins(ev0, my0, mine, T0, r0.need, lane, c_begin);
-    if (T0) guess = T0;
-
-    // Frame t + 1: every column's overlap given frame t's winners.
-    if (two) {
-      uint64_t fm[NV];
-      select_all(ev0, T0, r0.need, lane, fm);
-#pragma unroll
-      for (int u = 0; u < NV; ++u)
-        ev1[u] = ((vL[u] & ~fm[u]) | (vW[u] & fm[u])) & kFieldBits;
-      const uint32_t my1 = r0.sel ? lane_value(ovW, lane) : lane_value(ovL, lane);
-      const uint32_t T1 = topk_threshold(ev1, sh.S, sh.k, guess, &c_hi);
-      r1.T = T1;
-      r1.need = T1 ? sh.k - c_hi : 0u;
-      r1.nsel = T1 ? sh.k : c_hi;
-      r1.ov = my1;
-      r1.sel = own_wins(ev1, my1, mine, T1, r1.need, lane, c_begin);
-      if (T1) guess = T1;
-    }
-
-    // Learning, on the own columns that won: those that won frame t take the
-    // state learned from it, then those that win frame t + 1 learn from it.
-    uint32_t changed = 0;
-    if (a.learn) {
-      const uint32_t sel0 = (uint32_t)__ballot(r0.sel) & kAllCols;
-      const uint32_t sel1 = two ? (uint32_t)__ballot(r1.sel) & kAllCols : 0u;
-      changed = sel0 | sel1;
-#pragma unroll
-      for (uint32_t j = 0; j < CPW; ++j) {
-        if ((changed >> j) & 1u) {
-#pragma unroll
-          for (uint32_t rr = 0; rr < RPC; ++rr) {
-            const uint32_t r = j * RPC + rr;
-            if ((sel0 >> j) & 1u) {
-              st[r] = stW[r];
-              msk[r] = mskW[r];
-            }
-            if ((sel1 >> j) & 1u) {
-              const uint32_t i = st[r] >> 9;
-              const uint32_t q = learn_q(st[r] & 511u, input_bit(w1[r], i), sh);
-              const bool ok = (row_ok >> r) & 1u;
-              st[r] = ok ? (i << 9) | q : st[r];
-              msk[r] = ok ? (q >= sh.theta ? 1u << (i & 31u) : 0u) : msk[r];
-            }
-          }
-        }
-      }
-    }
-    prev_t = t;
-    prev_two = two;
-
-    // The next pair: the speculation, redone for the columns that learned.
-    if (has_next) {
-      if (changed) products(changed, n0, n1, sov0, sovL, sovW, sstW, smskW);
-#pragma unroll
-      for (uint32_t r = 0; r < ROWS; ++r) {
-        w0[r] = n0[r];
-        w1[r] = n1[r];
-        stW[r] = sstW[r];
-        mskW[r] = smskW[r];
-      }
-#pragma unroll
-      for (uint32_t j = 0; j < CPW; ++j) {
-        ov0[j] = sov0[j];
-        ovL[j] = sovL[j];
-        ovW[j] = sovW[j];
-      }
-    }
-  }
-
-  if (abort) {
-    lds_release(&ctl[2], 1u);
-    if (lane == 0) store_tagged(a.err, 1u);
-    return;
-  }
-  if (a.F > 0) {
-    write_frame(a, ev0, r0, prev_t, lane, mine, c_begin, blockIdx.x == 0);
-    if (prev_two) write_frame(a, ev1, r1, prev_t + 1, lane, mine, c_begin, blockIdx.x == 0);
-  }
-  if (a.learn) {
-#pragma unroll
-    for (uint32_t r = 0; r < ROWS; ++r) {
-      const uint32_t j = r / RPC, s = (r % RPC) * kWave + lane;
-      if ((row_ok >> r) & 1u) a.perm[(size_t)(c_begin + j) * sh.S + s] = q_to_perm(st[r] & 511u);
-    }
-  }
-}
-
-// Persistent multi-frame step, one column group per wave.  The same pair
-// protocol as k_sp_persistent (two frames per exchange, the next pair's
-// products computed while the exchange is in flight), but each workgroup
-// holds kPersistWaves waves and each wave owns CPW = RW / RPC consecutive
+// winners' own synapses; so each wave publishes, with its frame-t overlaps,
+// the frame-(t+1) overlaps its columns will have if they lose frame t and if
+// they win it.  Every wave resolves frame t's winners, picks each column's
+// frame-(t+1) overlap accordingly and resolves frame t + 1 as well, so one
+// exchange round trip serves two frames; the results are exactly those of
+// stepping the frames one by one.  The next pair's products are computed
+// while the exchange is in flight.  Each workgroup holds kPersistWaves
+// waves and each wave owns CPW = RW / RPC consecutive
 // columns (row r of the wave holds synapses (r % RPC) * 64 + lane of its
 // local column r / RPC), so the per-pair work that depends on a wave's
 // columns (products, learning, outputs) is split four ways, and the wave
@@ -944,28 +571,12 @@ __global__ __launch_bounds__(kPersistWaves * kWave) void k_sp_persistent_w(Persi
 
 }  // namespace
 
-size_t persistent_lds_bytes(uint32_t rows) {
-  return sizeof(uint32_t) * ((size_t)kRing * rows * kWave + 4);
-}
-
 uint32_t persistent_exchange_arrays() { return 3; }
 
 uint32_t persistent_exchange_entries(uint32_t C) {
   uint32_t nv = 1;
   while (nv * 4 * kWave < C) nv <<= 1;
   return nv * 4 * kWave;
-}
-
-const void* persistent_kernel(uint32_t rpc, uint32_t nv, uint32_t rows) {
-#define HTMSP_PK(P, V, R)                              \
-  if (rpc == P && nv == V && rows == R)                \
-    return reinterpret_cast<const void*>(&k_sp_persistent<P, V, R>);
-#define HTMSP_PK_V(P, R) \
-  HTMSP_PK(P, 1, R) HTMSP_PK(P, 2, R) HTMSP_PK(P, 4, R) HTMSP_PK(P, 8, R) HTMSP_PK(P, 16, R)
-  HTMSP_PK_V(1, 16) HTMSP_PK_V(2, 16) HTMSP_PK_V(4, 16) HTMSP_PK_V(8, 16) HTMSP_PK_V(16, 16)
-#undef HTMSP_PK_V
-#undef HTMSP_PK
-  return nullptr;
 }
 
 const void* persistent_wave_kernel(uint32_t rpc, uint32_t nv, uint32_t rw) {

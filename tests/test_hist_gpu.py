@@ -74,3 +74,23 @@ def test_many_instances():
                               oracle.histogram(e_win, w.cfg["num_columns"]))
     for p in pools:
         p.close()
+
+
+@pytest.mark.parametrize("C", [700, 1500])  # persistent boosted step, and the plain sequence
+def test_boosted_step(C):
+    import torch
+    bc = {"period_log2": 6, "min_pct_q16": 16384, "max_boost_q8": 2560, "bump_q8": 13}
+    cfg = synth.sp_config(100_000, C, 96, 3, 30)
+    w = synth.random_instance(37 + C, cfg, 24, density=0.08)
+    _, e_win, _, _ = oracle.run_boost(cfg, bc, w.idx, w.perm, w.frames, want_overlaps=False)
+    pool = sp.SpatialPooler(cfg, w.idx, w.perm)
+    assert pool.boost_kernel == ("k_sp_persistent_boost" if C <= 1024 else "plain")
+    h = _hist(C)
+    pool.set_histogram(h)
+    frames = torch.from_numpy(w.frames.view(np.int32)).cuda()
+    win = torch.empty((24, 30), dtype=torch.int32, device="cuda")
+    sp.sp_step_boost(pool.handle, cfg, bc, frames, True, None, win)
+    pool.sync()
+    assert np.array_equal(win.cpu().numpy(), e_win)
+    assert np.array_equal(h.cpu().numpy().astype(np.uint32), oracle.histogram(e_win, C))
+    pool.close()

@@ -31,7 +31,7 @@ namespace {
 using namespace dev;
 
 constexpr uint32_t kEncThreads = 256;
-constexpr uint32_t kBandRows = 32;
+constexpr uint32_t kBandRows = 64;
 
 __global__ __launch_bounds__(256) void k_zero(uint32_t* __restrict__ out, size_t n) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -39,7 +39,8 @@ __global__ __launch_bounds__(256) void k_zero(uint32_t* __restrict__ out, size_t
     out[i] = 0u;
 }
 
-template <int B>
+// ONE: no reduction (factor 1), the rows' loads issued ahead.
+template <int B, bool ONE>
 __global__ __launch_bounds__(kEncThreads) void k_encode(const uint8_t* __restrict__ rgb,
                                                         uint32_t F, EncShape e,
                                                         uint32_t* __restrict__ out) {
@@ -99,17 +100,44 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(const uint8_t* __restric
   for (int i = 0; i < B - 1; ++i) win[i + 1] = gray((uint32_t)min(max((int)y0 - R + i, 0), (int)e.h - 1));
   uint32_t* dst = out + (size_t)f * e.words;
   uint32_t buf = 0;
-  for (uint32_t y = y0; y < y1; ++y) {
+  // Without reduction, the RGB bytes of the row entering the window are
+  // loaded kAhead rows before they are needed, into a ring indexed by the
+  // unrolled row (so that no register with a load in flight is copied);
+  // loads past the band's last needed row read that row again.
+  constexpr int kAhead = 8;
+  uint32_t pr[kAhead], pg[kAhead], pb[kAhead];
+  const uint32_t last_row = min(y1 - 1 + R, e.h - 1);
+  auto issue = [&](int k, uint32_t gy) {
+    const uint8_t* px = src + 3 * ((size_t)min(gy, last_row) * e.W + xc);
+    pr[k] = px[0];
+    pg[k] = px[1];
+    pb[k] = px[2];
+  };
+  if constexpr (ONE) {
+#pragma unroll
+    for (int k = 0; k < kAhead; ++k) issue(k, y0 + R + k);
+  }
+  for (uint32_t yb = y0; yb < y1; yb += kAhead) {
+#pragma unroll
+  for (int k = 0; k < kAhead; ++k) {
+    const uint32_t y = yb + k;
 #pragma unroll
     for (int i = 0; i < B - 1; ++i) win[i] = win[i + 1];
-    win[B - 1] = gray((uint32_t)min((int)y + R, (int)e.h - 1));
+    if constexpr (ONE) {
+      win[B - 1] = (4899u * pr[k] + 9617u * pg[k] + 1868u * pb[k] + 8192u) >> 14;
+      issue(k, y + R + kAhead);
+    } else {
+      win[B - 1] = gray((uint32_t)min((int)y + R, (int)e.h - 1));
+    }
     uint32_t v = 0;
 #pragma unroll
     for (int i = 0; i < B; ++i) v += wt[i] * win[i];
     vrow[buf][tid] = v;
-    __syncthreads();
+    // The row of vertical sums is the only thing the barrier orders: wait for
+    // LDS only, so the row loads issued ahead stay in flight across it.
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
     bool on = false;
-    if (out_col) {
+    if (out_col && y < y1) {
       const uint32_t* vr = &vrow[buf][tid - R];
       uint32_t s = 0;
 #pragma unroll
@@ -135,6 +163,7 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(const uint8_t* __restric
     }
     buf ^= 1u;
   }
+  }
 }
 
 }  // namespace
@@ -152,9 +181,14 @@ hipError_t launch_encode(const uint8_t* rgb, uint32_t F, const EncShape& e, uint
   const uint32_t strips = (e.w + tw - 1) / tw;
   const uint32_t bands = (e.h + kBandRows - 1) / kBandRows;
   const uint32_t blocks = (F + 7) / 8 * 8 * strips * bands;
-#define HTMSP_ENC(B)                                                                      \
-  case B:                                                                                 \
-    hipLaunchKernelGGL(k_encode<B>, dim3(blocks), dim3(kEncThreads), 0, s, rgb, F, e, out); \
+#define HTMSP_ENC(B)                                                                        \
+  case B:                                                                                   \
+    if (e.factor == 1)                                                                      \
+      hipLaunchKernelGGL((k_encode<B, true>), dim3(blocks), dim3(kEncThreads), 0, s, rgb, F, \
+                         e, out);                                                           \
+    else                                                                                    \
+      hipLaunchKernelGGL((k_encode<B, false>), dim3(blocks), dim3(kEncThreads), 0, s, rgb,  \
+                         F, e, out);                                                        \
     break;
   switch (e.block) {
     HTMSP_ENC(3) HTMSP_ENC(5) HTMSP_ENC(7) HTMSP_ENC(9) HTMSP_ENC(11)

@@ -117,10 +117,11 @@ int sp_check_state(sp_handle* h, void* stream);
  * overlaps may be NULL; winners must not be.  F == 0 is a no-op.
  *
  * The frames run in one persistent launch that keeps the handle's synapse
- * state on chip (one workgroup per group of columns, the per-frame overlaps
- * exchanged through device memory); shapes it cannot hold run as
- * sp_step_plain.  A device-side failure of the persistent launch is reported
- * by the next sp_sync. */
+ * state in registers (a group of columns per wave, one workgroup per CU, the
+ * per-frame overlaps exchanged through device memory, two frames per
+ * exchange); shapes it cannot hold (see sp_step_kernel) run as
+ * sp_step_plain, with the same results.  A device-side failure of the
+ * persistent launch is reported by the next sp_sync. */
 int sp_step(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames, int learn,
             int32_t* overlaps_dev, int32_t* winners_dev, void* stream);
 

@@ -192,7 +192,7 @@ hipError_t launch_hist_add(const int32_t* winners, size_t n, uint32_t C, uint32_
 
 // Many instances in one persistent launch (sp_many.hip).
 constexpr uint32_t kManyNV = 16;          // top-k words per lane: C <= 4096
-constexpr uint32_t kTileSynapses = 8192;  // synapses per tile task (at most)
+constexpr uint32_t kTileSynapses = 4096;  // synapses per tile task (at most)
 constexpr uint32_t kTileColumns = 1024;   // columns per tile task (at most)
 constexpr uint32_t kManyThreads = 256;
 constexpr uint32_t kMaxTileSlots = 16;    // tile tasks per workgroup (at most)

@@ -11,7 +11,7 @@
 //     the whole workgroup: once the instance's decision of step t-1 is out,
 //     its step t applies learning of frame t-1 to its winning columns, then
 //     computes the overlaps of frame t and publishes them.  Each thread owns
-//     up to 32 synapses of the tile's flat [column][synapse] range and issues
+//     up to 16 synapses of the tile's flat [column][synapse] range and issues
 //     all their state loads, then both input gathers, at once; per-column
 //     counts are summed in LDS, and each tile keeps its last published
 //     overlaps in LDS to decide its winners.  A workgroup steps whichever of
@@ -40,7 +40,7 @@ namespace {
 
 using namespace dev;
 
-constexpr uint32_t kPerThread = kTileSynapses / kManyThreads;  // 32
+constexpr uint32_t kPerThread = kTileSynapses / kManyThreads;  // 16
 
 // The instance descriptors live in device memory, so the compiler cannot
 // tell that their pointers address global memory and would use flat

@@ -29,6 +29,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+INT8_PEAK_TOPS = 5000.0  # MI355X dense int8 matrix throughput, published (TOP/s)
 PROFILES = os.path.join(ROOT, "profiles")
 
 
@@ -203,10 +204,13 @@ def bench_infer(args, torch, sp, synth):
     ov = torch.empty((F, C), dtype=torch.int32, device="cuda")
     win = torch.empty((F, k), dtype=torch.int32, device="cuda")
 
+    mfma = args.infer_mode == "mfma"
+    mode = sp.SP_INFER_MFMA_I8 if mfma else sp.SP_INFER_GATHER
+
     def run(ev0=None, ev1=None):
         if ev0 is not None:
             ev0.record(stream)
-        sp.sp_infer(pool.handle, cfg, frames, sp.SP_INFER_GATHER, ov, win, stream)
+        sp.sp_infer(pool.handle, cfg, frames, mode, ov, win, stream)
         if ev1 is not None:
             ev1.record(stream)
 
@@ -218,10 +222,29 @@ def bench_infer(args, torch, sp, synth):
     pool.sync()
     fps = args.steps * F / wall_s
     abytes = algorithmic_bytes_infer(cfg, F)
-    achieved = abytes / (call_ms * 1e-3) / 1e9
-    traffic, traffic_bytes = measured_traffic("k_infer_gather_960x540_1024c_256s.md",
-                                              "k_infer_gather_db+k_topk_batch",
-                                              call_ms)
+    hbm_achieved = abytes / (call_ms * 1e-3) / 1e9
+    if mfma:
+        # the dense product: 2 F N C int8 operations (multiply and add) per call
+        aops = 2 * F * cfg["input_bits"] * C
+        achieved = aops / (call_ms * 1e-3) / 1e12
+        traffic, traffic_bytes = measured_traffic("k_infer_mfma_960x540_1024c_256s.md",
+                                                  "k_infer_mfma+k_mfma_reduce+k_topk_batch",
+                                                  call_ms)
+        roof = {"bound": "mfma", "achieved": achieved, "peak": INT8_PEAK_TOPS,
+                "unit": "TOP/s", "frac": achieved / INT8_PEAK_TOPS, "traffic": traffic,
+                "kernel": "k_infer_mfma + k_mfma_reduce + k_topk_batch",
+                "kernel_ms_per_launch": call_ms, "algorithmic_ops_per_launch": aops,
+                "algorithmic_bytes_per_launch": abytes, "hbm_achieved_gbs": hbm_achieved,
+                "counter_bytes_per_launch": traffic_bytes}
+    else:
+        traffic, traffic_bytes = measured_traffic("k_infer_gather_960x540_1024c_256s.md",
+                                                  "k_infer_gather_db+k_topk_batch",
+                                                  call_ms)
+        roof = {"bound": "hbm", "achieved": hbm_achieved, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": hbm_achieved / HBM_PEAK_GBS, "traffic": traffic,
+                "kernel": "k_infer_gather_db + k_topk_batch", "kernel_ms_per_launch": call_ms,
+                "algorithmic_bytes_per_launch": abytes,
+                "counter_bytes_per_launch": traffic_bytes}
 
     # the same frames one launch sequence at a time, and through the
     # persistent sequential step with learning off
@@ -242,22 +265,20 @@ def bench_infer(args, torch, sp, synth):
     cpu = None if args.no_cpu_baseline else cpu_baseline(
         w, False, args.cpu_budget, f"{F}-frame inference batch")
     line = {
-        "metric": "SP frames/s (1024 columns x 256 synapses, batched inference, learning off)",
+        "metric": "SP frames/s (1024 columns x 256 synapses, batched inference, learning off"
+                  + (", dense int8 matrix product)" if mfma else ")"),
         "value": fps, "unit": "frames/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": wall_s / args.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "u32", "data": "synthetic",
+        "dtype": "i8" if mfma else "u32", "data": "synthetic",
         "config": {"workload": f"{F} independent 960x540 Bernoulli(0.05) frames per step, "
                                f"frozen {C} columns x {S} synapses, min_overlap "
                                f"{cfg['min_overlap']}, {k} winners",
                    "frames_per_step": F, "columns": C, "synapses": S,
-                   "input_bits": cfg["input_bits"], "winners": k, "path": "gather"},
+                   "input_bits": cfg["input_bits"], "winners": k,
+                   "path": "mfma_i8" if mfma else "gather"},
         "synapse_updates_per_s": fps * C * S,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_infer_gather_db + k_topk_batch", "kernel_ms_per_launch": call_ms,
-                     "algorithmic_bytes_per_launch": abytes,
-                     "counter_bytes_per_launch": traffic_bytes},
+        "roofline": roof,
         **comp,
         "cpu_baseline": cpu,
     }
@@ -648,6 +669,8 @@ def main() -> int:
                     help="untimed busy time before the timed steps (GPU clock ramp-up)")
     ap.add_argument("--frames", type=int, default=1000)
     ap.add_argument("--infer-frames", type=int, default=4096)
+    ap.add_argument("--infer-mode", choices=["gather", "mfma"], default="gather",
+                    help="sp_infer mode of --workload infer")
     ap.add_argument("--columns", type=int, default=1024)
     ap.add_argument("--synapses", type=int, default=256)
     ap.add_argument("--plain-frames", type=int, default=200,

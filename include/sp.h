@@ -133,16 +133,31 @@ int sp_step_plain(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames,
 /* Batched inference (Section 4.1's testing mode, learning off): overlap
  * and global inhibition of F independent frames against the handle's
  * current state, which is left unchanged.  Results equal sp_step with
- * learn = 0 frame by frame.
+ * learn = 0 frame by frame, in either mode.
  *
  * mode SP_INFER_GATHER compacts every column's connected synapses once per
  * state change (a step that learned, or sp_check_state), then counts active
  * inputs by gathering bits of each frame staged in LDS.  The first call
  * after a state change synchronises `stream` (it reads back the longest
  * connected list); SP_EINVAL if that list exceeds 256 synapses.
+ *
+ * mode SP_INFER_MFMA_I8 computes the overlaps as one dense matrix product,
+ * frames (0/1 per pixel) times the connected mask (1 where a connected
+ * synapse of the column sits on the pixel), both widened from bits to int8
+ * in registers and accumulated in int32 by the matrix cores, then gates and
+ * selects as the gather mode does.  The mask, C x ceil(N / 512) x 64 bytes,
+ * is built once per state change (that first call synchronises `stream`);
+ * SP_EINVAL if it would exceed 4 GiB or if two connected synapses of one
+ * column share a pixel (a 0/1 mask cannot count them).  Frames and mask
+ * stay bit-packed; there is no limit on connected synapses per column.
+ *
  * overlaps may be NULL (the library then keeps an internal [F][C] buffer,
- * grown on demand); winners must not be. */
+ * grown on demand); winners must not be.  Library-owned buffers, freed by
+ * sp_destroy: gather lists 4 (S C + C + 64) bytes; the mask plus 256 bytes;
+ * for the matrix product on few frames (F x C below about 2^24), partial
+ * sums of up to 8 pixel ranges, 4 x ranges x F x C bytes. */
 #define SP_INFER_GATHER 0
+#define SP_INFER_MFMA_I8 1
 int sp_infer(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames, int mode,
              int32_t* overlaps_dev, int32_t* winners_dev, void* stream);
 
@@ -154,9 +169,15 @@ int sp_infer(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames, int 
  * handle i (0 = skip it), winners_dev[i] is [num_frames[i]][k_i],
  * overlaps_dev may be NULL or hold NULL entries.  Handles must be distinct,
  * on one device, with at most 4096 columns each.  Results equal stepping each
- * handle alone.  A device-side failure is reported by sp_sync on hs[0].
- * Calls are serialised by the library; one call's launch must not overlap
- * another call's on a different stream. */
+ * handle alone.  Instances beyond what one launch holds go into further
+ * launches on the same stream.  A device-side failure (a wait that gives up)
+ * is reported by sp_sync on every handle whose steps it may have cut short;
+ * a handle of the failing launch whose steps all completed reports nothing
+ * and holds the results of stepping it alone.  If a
+ * launch cannot be enqueued, the call returns SP_EDEVICE: the handles of
+ * earlier launches of the call were stepped, those of the failed launch and
+ * later ones are broken (SP_EBROKEN).  Calls are serialised by the library;
+ * one call's launch must not overlap another call's on a different stream. */
 int sp_step_many(sp_handle* const* hs, uint32_t n, const uint32_t* const* frames_dev,
                  const uint32_t* num_frames, int learn, int32_t* const* overlaps_dev,
                  int32_t* const* winners_dev, void* stream);
@@ -200,6 +221,39 @@ int sp_boost_state(sp_handle* h, uint32_t* active_duty_dev, uint32_t* overlap_du
 
 /* Duty cycles back to 0 and boosts to 1. */
 int sp_boost_reset(sp_handle* h, void* stream);
+
+/* Checkpoint and resume (the pooler as a unit that keeps learning across
+ * sessions, Section 3.2.1, and switches between learning and testing,
+ * Section 4.1).  The state of a handle is its borrowed idx and perm, the
+ * count of learning frames it has applied (every step with learn != 0 adds
+ * its frame count), and the boost state of sp_step_boost.  Stepping a
+ * handle restored from a checkpoint gives the same results as stepping the
+ * handle the checkpoint was taken from.
+ *
+ * sp_state_bytes: bytes of idx plus perm, 8 C S (0 on a bad configuration).
+ * sp_get_state: copies idx [C][S] and perm [C][S] into host memory (either
+ *   may be NULL) and the frame count into *frames_seen (may be NULL), then
+ *   synchronises `stream`.
+ * sp_set_state: checks the host arrays (idx < N, permanences on the 1/256
+ *   grid in [0, 1]; SP_EINVAL names the first bad entry, nothing changes),
+ *   copies them into the handle's borrowed device buffers (idx NULL keeps
+ *   the pools), sets the frame count and synchronises `stream`.  A failed
+ *   copy breaks the handle.
+ * sp_get_boost_state / sp_set_boost_state: the boost state, uint32 [C]
+ *   each, in host memory (duty cycles 0..65536, boosts 256..4096; the setter
+ *   checks these ranges and needs all three arrays); both synchronise
+ *   `stream`.  A handle that never boosted reports duty cycles 0 and boosts
+ *   1 (256). */
+size_t sp_state_bytes(const sp_config* cfg);
+int sp_get_state(sp_handle* h, uint32_t* idx_host, float* perm_host, uint64_t* frames_seen,
+                 void* stream);
+int sp_set_state(sp_handle* h, const uint32_t* idx_host, const float* perm_host,
+                 uint64_t frames_seen, void* stream);
+int sp_get_boost_state(sp_handle* h, uint32_t* active_duty_host, uint32_t* overlap_duty_host,
+                       uint32_t* boost_host, void* stream);
+int sp_set_boost_state(sp_handle* h, const uint32_t* active_duty_host,
+                       const uint32_t* overlap_duty_host, const uint32_t* boost_host,
+                       void* stream);
 
 /* Local inhibition, Algorithm 2 as printed: every column competes within
  * the neighbourhood an inhibition radius gives it (Section 3.2.2), instead
@@ -293,11 +347,13 @@ int sp_step_local_kernel(const sp_handle* h);
 int sp_step_boost_kernel(const sp_handle* h);
 
 /* For tests of the failure path (callers: test suites, not applications):
- * the next persistent launch of sp_step, sp_step_local or sp_step_boost on
- * this handle waits for exchange entries that are never written, giving up
- * after `spin_limit` polls (1..2^21) as a stalled exchange would, so that
- * every wave leaves its loop and the launch drains; sp_sync then reports
- * SP_EDEVICE and the handle is broken.  Applies to one launch; a plain
+ * the next persistent launch of sp_step, sp_step_local, sp_step_boost or
+ * sp_step_many that holds this handle waits for exchange entries that are
+ * never written, giving up after `spin_limit` polls (1..2^21) as a stalled
+ * exchange would, so that every wave leaves its loop and the launch drains;
+ * sp_sync then reports SP_EDEVICE (for sp_step_many: on this handle and on
+ * every other handle whose steps the launch cut short) and the handle is
+ * broken.  Applies to one launch; a plain
  * (non-persistent) step ignores it.  SP_EINVAL on a bad handle or limit. */
 int sp_test_stall(sp_handle* h, uint32_t spin_limit);
 

@@ -20,8 +20,8 @@ import ctypes
 import numpy as np
 
 from . import _native, synth
-from ._native import (SP_EBROKEN, SP_EDEVICE, SP_EINVAL, SP_ENOMEM, SP_INFER_GATHER, SP_OK,
-                      SpConfig, lib)
+from ._native import (SP_EBROKEN, SP_EDEVICE, SP_EINVAL, SP_ENOMEM, SP_INFER_GATHER,
+                      SP_INFER_MFMA_I8, SP_OK, SpConfig, lib)
 
 __all__ = [
     "SpError", "SpatialPooler", "synth", "sp_config_check", "sp_frame_words",
@@ -29,11 +29,12 @@ __all__ = [
     "sp_step_plain", "sp_infer", "sp_step_many", "sp_set_histogram", "sp_encode",
     "sp_inhibit_local", "sp_step_local", "sp_step_boost", "sp_boost_state", "sp_boost_reset",
     "sp_encoded_bits", "sp_step_is_persistent", "sp_step_kernel", "sp_step_local_kernel",
-    "sp_step_boost_kernel", "sp_test_stall", "STEP_KERNELS",
+    "sp_step_boost_kernel", "sp_test_stall", "STEP_KERNELS", "sp_state_bytes", "sp_get_state",
+    "sp_set_state", "sp_get_boost_state", "sp_set_boost_state",
     "sp_sync",
     "sp_destroy",
     "sp_last_error", "SP_OK", "SP_EINVAL", "SP_ENOMEM", "SP_EDEVICE", "SP_EBROKEN",
-    "SP_INFER_GATHER",
+    "SP_INFER_GATHER", "SP_INFER_MFMA_I8",
 ]
 
 
@@ -311,6 +312,61 @@ def sp_test_stall(h: int, spin_limit: int) -> None:
     _check(lib().sp_test_stall(ctypes.c_void_p(h), spin_limit), "sp_test_stall")
 
 
+def _host_ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def sp_state_bytes(cfg) -> int:
+    """Bytes of a handle's idx plus perm (0 for a bad configuration)."""
+    c = _cfg(cfg)
+    return int(lib().sp_state_bytes(ctypes.byref(c)))
+
+
+def sp_get_state(h: int, cfg, stream=None):
+    """(idx uint32 [C][S], perm float32 [C][S], frames_seen) in host memory."""
+    c = _cfg(cfg)
+    shape = (c.num_columns, c.synapses_per_column)
+    idx = np.empty(shape, dtype=np.uint32)
+    perm = np.empty(shape, dtype=np.float32)
+    seen = ctypes.c_uint64()
+    _check(lib().sp_get_state(ctypes.c_void_p(h), _host_ptr(idx), _host_ptr(perm),
+                              ctypes.byref(seen), _stream(stream)), "sp_get_state")
+    return idx, perm, int(seen.value)
+
+
+def sp_set_state(h: int, cfg, idx, perm, frames_seen: int = 0, stream=None) -> None:
+    """Loads host arrays idx (or None: keep the pools) and perm into the
+    handle's device state."""
+    c = _cfg(cfg)
+    n = c.num_columns * c.synapses_per_column
+    perm = np.ascontiguousarray(perm, dtype=np.float32)
+    if perm.size != n:
+        raise ValueError("perm must hold num_columns * synapses_per_column entries")
+    pi = None
+    if idx is not None:
+        idx = np.ascontiguousarray(idx, dtype=np.uint32)
+        if idx.size != n:
+            raise ValueError("idx must hold num_columns * synapses_per_column entries")
+        pi = _host_ptr(idx)
+    _check(lib().sp_set_state(ctypes.c_void_p(h), pi, _host_ptr(perm), int(frames_seen),
+                              _stream(stream)), "sp_set_state")
+
+
+def sp_get_boost_state(h: int, num_columns: int, stream=None):
+    """(active duty, overlap duty, boost) as uint32 host arrays [C]."""
+    out = [np.empty(num_columns, dtype=np.uint32) for _ in range(3)]
+    _check(lib().sp_get_boost_state(ctypes.c_void_p(h), *(_host_ptr(a) for a in out),
+                                    _stream(stream)), "sp_get_boost_state")
+    return tuple(out)
+
+
+def sp_set_boost_state(h: int, active_duty, overlap_duty, boost, stream=None) -> None:
+    """Loads the boost state from uint32 host arrays [C]."""
+    arrs = [np.ascontiguousarray(a, dtype=np.uint32) for a in (active_duty, overlap_duty, boost)]
+    _check(lib().sp_set_boost_state(ctypes.c_void_p(h), *(_host_ptr(a) for a in arrs),
+                                    _stream(stream)), "sp_set_boost_state")
+
+
 def sp_sync(h: int, stream=None) -> None:
     _check(lib().sp_sync(ctypes.c_void_p(h), _stream(stream)), "sp_sync")
 
@@ -391,6 +447,14 @@ class SpatialPooler:
         win = torch.empty((F, self.cfg["winners"]), dtype=torch.int32, device=self.idx.device)
         sp_infer(self.handle, self.cfg, frames, mode, ov, win, stream)
         return ov, win
+
+    def get_state(self, stream=None):
+        """Checkpoint: (idx, perm, frames_seen) in host memory."""
+        return sp_get_state(self.handle, self.cfg, stream)
+
+    def set_state(self, idx, perm, frames_seen: int = 0, stream=None) -> None:
+        """Resume from a checkpoint taken by get_state (idx None keeps the pools)."""
+        sp_set_state(self.handle, self.cfg, idx, perm, frames_seen, stream)
 
     def set_histogram(self, hist=None) -> None:
         """Accumulate every later call's winners into `hist` (GPU int32 [C],

@@ -15,6 +15,7 @@ SP_MAX_INPUT_BITS = 1 << 23
 SP_MAX_COLUMNS = 65536
 SP_MAX_SYNAPSES = 4096
 SP_INFER_GATHER = 0
+SP_INFER_MFMA_I8 = 1
 
 
 class SpConfig(ctypes.Structure):
@@ -84,6 +85,11 @@ SIGNATURES = [
     ("sp_step_local_kernel", ctypes.c_int, [P]),
     ("sp_step_boost_kernel", ctypes.c_int, [P]),
     ("sp_test_stall", ctypes.c_int, [P, ctypes.c_uint32]),
+    ("sp_state_bytes", ctypes.c_size_t, [CFG]),
+    ("sp_get_state", ctypes.c_int, [P, P, P, ctypes.POINTER(ctypes.c_uint64), P]),
+    ("sp_set_state", ctypes.c_int, [P, P, P, ctypes.c_uint64, P]),
+    ("sp_get_boost_state", ctypes.c_int, [P, P, P, P, P]),
+    ("sp_set_boost_state", ctypes.c_int, [P, P, P, P, P]),
     ("sp_sync", ctypes.c_int, [P, P]),
     ("sp_destroy", ctypes.c_int, [P]),
     ("sp_last_error", ctypes.c_char_p, []),

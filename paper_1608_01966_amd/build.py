@@ -9,7 +9,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB_DIR = os.path.join(PKG, "_lib")
 LIB_PATH = os.path.join(LIB_DIR, "libhtmsp.so")
-SOURCES = ["sp_kernels.hip", "sp_infer.hip", "sp_many.hip", "sp_hist.hip", "sp_encode.hip",
+SOURCES = ["sp_kernels.hip", "sp_infer.hip", "sp_infer_mfma.hip", "sp_many.hip", "sp_hist.hip", "sp_encode.hip",
            "sp_local.hip", "sp_boost.hip", "sp_api.hip"]
 ARCH = "gfx950"
 

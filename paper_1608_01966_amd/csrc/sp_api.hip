@@ -36,6 +36,7 @@ struct sp_handle {
   uint32_t boost_C;    // columns the boost state was set up for (0: none yet)
   uint64_t* many_dec;  // decision word of the many-instance step
   uint32_t many_steps; // steps this handle has taken through sp_step_many
+  uint64_t frames_seen; // learning frames applied to the state (sp_get_state)
   uint64_t xchg_frames;
   bool persistent;
   uint32_t grid, block, replicas;
@@ -63,6 +64,14 @@ struct sp_handle {
   uint64_t infer_version;    // state version the lists were built for (0: none)
   int32_t* infer_ov;         // [capacity][C] overlaps when the caller wants none
   uint32_t infer_ov_frames;
+  // int8 matrix-product inference: bit mask [C][Wm] of the connected
+  // synapses plus a duplicate counter, the state version it was built for,
+  // the duplicates it found, and the partial sums of the pixel splits
+  uint32_t* mfma_mask;
+  uint64_t mfma_version;
+  uint32_t mfma_dups;
+  int32_t* mfma_part;
+  size_t mfma_part_elems;
 };
 
 namespace {
@@ -164,6 +173,14 @@ int check_handle(const sp_handle* h) {
   if (!h) return fail(SP_EINVAL, "handle is NULL");
   if (h->broken) return fail(SP_EBROKEN, "handle saw a device failure; destroy it");
   return SP_OK;
+}
+
+// A call that learned on F frames changed the state: batched inference
+// rebuilds what it derives from it, and the frame count moves on.
+void note_learned(sp_handle* h, uint32_t F, int learn) {
+  if (!learn || F == 0) return;
+  ++h->state_version;
+  h->frames_seen += F;
 }
 
 int check_step_args(const sp_handle* h, const uint32_t* frames, uint32_t F, int32_t* ov,
@@ -330,7 +347,7 @@ int many_slot(int device, size_t bytes, ManySlot** out) {
 int many_launch(sp_handle* const* hs, uint32_t n, const uint32_t* const* frames_dev,
                 const uint32_t* num_frames, int learn, int32_t* const* overlaps_dev,
                 int32_t* const* winners_dev, hipStream_t s, int dev, int maxb, bool aligned,
-                size_t ntiles, uint32_t nact, uint32_t Fmax, uint32_t* err) {
+                size_t ntiles, uint32_t nact, uint32_t Fmax) {
   const uint32_t ntasks = (uint32_t)(ntiles + nact);
   const uint32_t kblocks = htmsp::many_topk_blocks(nact, (size_t)maxb);
   const uint32_t tblocks = (uint32_t)std::min<size_t>(ntiles, (size_t)maxb - kblocks);
@@ -338,7 +355,7 @@ int many_launch(sp_handle* const* hs, uint32_t n, const uint32_t* const* frames_
   std::vector<std::vector<htmsp::ManyTask>> per(grid);
   std::vector<htmsp::ManyInst> insts;
   insts.reserve(nact);
-  uint32_t next_tile = 0, next_topk = 0;
+  uint32_t next_tile = 0, next_topk = 0, spin_limit = kSpinLimit;
   for (uint32_t i = 0; i < n; ++i) {
     sp_handle* h = hs[i];
     if (num_frames[i] == 0) continue;
@@ -357,6 +374,11 @@ int many_launch(sp_handle* const* hs, uint32_t n, const uint32_t* const* frames_
     in.step_base = h->many_steps;
     in.guess = 1 + h->sh.S / 16;
     in.smagic = h->sh.S == 1 ? 0u : (uint32_t)(((1ull << 32) + h->sh.S - 1) / h->sh.S);
+    in.err = h->err;
+    if (h->stall_spins) {
+      in.stall = 1;
+      spin_limit = std::min(spin_limit, h->stall_spins);
+    }
     insts.push_back(in);
     const uint32_t ct = htmsp::many_tile_columns(h->sh.S);
     for (uint32_t c0 = 0; c0 < h->sh.C; c0 += ct)
@@ -365,14 +387,19 @@ int many_launch(sp_handle* const* hs, uint32_t n, const uint32_t* const* frames_
   for (uint32_t id = 0; id < insts.size(); ++id)
     per[tblocks + (next_topk++ % kblocks)].push_back({id, 1u, 0u, 0u});
 
+  // staging layout: the launch's error word (cleared by the upload), the
+  // instance descriptors, the tasks, the per-workgroup task offsets
+  const size_t b_err = 256;
   const size_t b_insts = align_up(sizeof(htmsp::ManyInst) * insts.size(), 256);
   const size_t b_tasks = align_up(sizeof(htmsp::ManyTask) * ntasks, 256);
   const size_t b_off = sizeof(uint32_t) * (grid + 1);
   ManySlot* sl = nullptr;
-  int rc = many_slot(dev, b_insts + b_tasks + b_off, &sl);
+  int rc = many_slot(dev, b_err + b_insts + b_tasks + b_off, &sl);
   if (rc) return rc;
   char* hb = static_cast<char*>(sl->host);
   char* db = static_cast<char*>(sl->dev);
+  memset(hb, 0, b_err);
+  hb += b_err;
   memcpy(hb, insts.data(), sizeof(htmsp::ManyInst) * insts.size());
   htmsp::ManyTask* ht = reinterpret_cast<htmsp::ManyTask*>(hb + b_insts);
   uint32_t* hoff = reinterpret_cast<uint32_t*>(hb + b_insts + b_tasks);
@@ -382,19 +409,28 @@ int many_launch(sp_handle* const* hs, uint32_t n, const uint32_t* const* frames_
     for (const auto& t : per[b]) ht[k++] = t;
   }
   hoff[grid] = k;
-  hipError_t e = hipMemcpyAsync(db, hb, b_insts + b_tasks + b_off, hipMemcpyHostToDevice, s);
+  hipError_t e = hipMemcpyAsync(db, hb - b_err, b_err + b_insts + b_tasks + b_off,
+                                hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return hip_fail(e, "many-instance descriptors");
   htmsp::ManyArgs a = {};
+  a.err = reinterpret_cast<uint32_t*>(db);
+  db += b_err;
   a.insts = reinterpret_cast<htmsp::ManyInst*>(db);
   a.tasks = reinterpret_cast<const htmsp::ManyTask*>(db + b_insts);
   a.task_off = reinterpret_cast<const uint32_t*>(db + b_insts + b_tasks);
-  a.err = err;
   a.Fmax = Fmax;
   a.learn = learn ? 1u : 0u;
-  a.spin_limit = kSpinLimit;
+  a.spin_limit = spin_limit;
   e = htmsp::launch_many(a, grid, aligned, s);
   if (e == hipSuccess) e = hipEventRecord(sl->done, s);
   if (e != hipSuccess) return hip_fail(e, "many-instance launch");
+  // the launch is enqueued: every instance it holds has moved on
+  for (uint32_t i = 0; i < n; ++i) {
+    if (num_frames[i] == 0) continue;
+    hs[i]->many_steps += num_frames[i];
+    hs[i]->stall_spins = 0;
+    note_learned(hs[i], num_frames[i], learn);
+  }
   return SP_OK;
 }
 
@@ -504,7 +540,7 @@ int sp_step_plain(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames,
   DeviceScope ds(h->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
   const Shape& sh = h->sh;
-  if (learn && num_frames) ++h->state_version;
+  note_learned(h, num_frames, learn);
   for (uint32_t t = 0; t < num_frames; ++t) {
     const uint32_t* frame = frames_dev + (size_t)t * sh.W;
     int32_t* ov = overlaps_dev ? overlaps_dev + (size_t)t * sh.C : h->ov_scratch;
@@ -546,18 +582,48 @@ int sp_step(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames, int l
                                             static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "persistent step launch");
   h->xchg_frames += (num_frames + 1) / 2;
-  if (learn) ++h->state_version;
+  note_learned(h, num_frames, learn);
   return add_histogram(h, winners_dev, num_frames, static_cast<hipStream_t>(stream));
 }
 
-int sp_infer(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames, int mode,
-             int32_t* overlaps_dev, int32_t* winners_dev, void* stream) {
-  int rc = check_step_args(h, frames_dev, num_frames, overlaps_dev, winners_dev);
-  if (rc) return rc;
-  if (mode != SP_INFER_GATHER) return fail(SP_EINVAL, "unknown inference mode %d", mode);
-  if (num_frames == 0) return ok();
-  DeviceScope ds(h->device);
-  hipStream_t s = static_cast<hipStream_t>(stream);
+}  // extern "C"
+
+namespace {
+
+// The [F][C] overlap buffer sp_infer uses when the caller passes none.
+int infer_ov_scratch(sp_handle* h, uint32_t F, int32_t** out) {
+  if (h->infer_ov_frames < F) {
+    if (h->infer_ov) {
+      hipError_t e = hipFree(h->infer_ov);
+      h->infer_ov = nullptr;
+      h->infer_ov_frames = 0;
+      if (e != hipSuccess) return hip_fail(e, "inference scratch free");
+    }
+    const size_t bytes = sizeof(int32_t) * (size_t)F * h->sh.C;
+    hipError_t e = hipMalloc(&h->infer_ov, bytes);
+    if (e != hipSuccess) {
+      h->infer_ov = nullptr;
+      return fail(SP_ENOMEM, "inference scratch hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    }
+    h->infer_ov_frames = F;
+  }
+  *out = h->infer_ov;
+  return SP_OK;
+}
+
+// Winners of F frames from their gated overlaps, and the histogram.
+int infer_topk(sp_handle* h, const int32_t* ov, uint32_t F, int32_t* winners, hipStream_t s) {
+  hipError_t e;
+  if (h->sh.C <= htmsp::kPersistMaxColumns)
+    e = htmsp::launch_topk_batch(ov, F, h->sh, winners, s);
+  else
+    e = htmsp::launch_topk_plain(ov, winners, h->sh, s, F);
+  if (e != hipSuccess) return hip_fail(e, "inference top-k launch");
+  return add_histogram(h, winners, F, s);
+}
+
+int infer_gather(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames,
+                 int32_t* overlaps_dev, int32_t* winners_dev, hipStream_t s) {
   const Shape& sh = h->sh;
   hipError_t e = hipSuccess;
   if (!h->infer_list) {
@@ -586,32 +652,101 @@ int sp_infer(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames, int 
                 h->infer_maxn, htmsp::infer_max_list());
   int32_t* ov = overlaps_dev;
   if (!ov) {
-    if (h->infer_ov_frames < num_frames) {
-      if (h->infer_ov) {
-        e = hipFree(h->infer_ov);
-        h->infer_ov = nullptr;
-        h->infer_ov_frames = 0;
-        if (e != hipSuccess) return hip_fail(e, "inference scratch free");
-      }
-      const size_t bytes = sizeof(int32_t) * (size_t)num_frames * sh.C;
-      e = hipMalloc(&h->infer_ov, bytes);
-      if (e != hipSuccess) {
-        h->infer_ov = nullptr;
-        return fail(SP_ENOMEM, "inference scratch hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
-      }
-      h->infer_ov_frames = num_frames;
-    }
-    ov = h->infer_ov;
+    int rc = infer_ov_scratch(h, num_frames, &ov);
+    if (rc) return rc;
   }
   e = htmsp::launch_infer_gather(h->infer_maxn, frames_dev, num_frames, h->infer_list,
                                  h->infer_cnt, sh, ov, (uint32_t)h->cus, s);
   if (e != hipSuccess) return hip_fail(e, "inference gather launch");
-  if (sh.C <= htmsp::kPersistMaxColumns)
-    e = htmsp::launch_topk_batch(ov, num_frames, sh, winners_dev, s);
-  else
-    e = htmsp::launch_topk_plain(ov, winners_dev, sh, s, num_frames);
-  if (e != hipSuccess) return hip_fail(e, "inference top-k launch");
-  return add_histogram(h, winners_dev, num_frames, s);
+  return infer_topk(h, ov, num_frames, winners_dev, s);
+}
+
+// Largest bit mask the matrix-product inference builds (C * Wm words).
+constexpr size_t kMfmaMaskMaxBytes = size_t(1) << 32;
+
+int infer_mfma(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames,
+               int32_t* overlaps_dev, int32_t* winners_dev, hipStream_t s) {
+  const Shape& sh = h->sh;
+  const size_t Wm = htmsp::mfma_mask_words(sh.W);
+  const size_t mask_bytes = sizeof(uint32_t) * Wm * sh.C;
+  if (mask_bytes > kMfmaMaskMaxBytes)
+    return fail(SP_EINVAL,
+                "the connected mask of %u columns x %u words exceeds %zu bytes; use the gather mode",
+                sh.C, (unsigned)Wm, kMfmaMaskMaxBytes);
+  hipError_t e = hipSuccess;
+  if (!h->mfma_mask) {
+    e = hipMalloc(&h->mfma_mask, mask_bytes + 256);
+    if (e != hipSuccess) {
+      h->mfma_mask = nullptr;
+      return fail(SP_ENOMEM, "connected mask hipMalloc(%zu): %s", mask_bytes + 256,
+                  hipGetErrorString(e));
+    }
+  }
+  uint32_t* dup = h->mfma_mask + Wm * sh.C;
+  if (h->mfma_version != h->state_version) {
+    e = htmsp::launch_mfma_mask(h->idx, h->perm, sh, h->mfma_mask, dup, s);
+    uint32_t dups = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&dups, dup, sizeof(dups), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "connected mask");
+    h->mfma_dups = dups;
+    h->mfma_version = h->state_version;
+  }
+  if (h->mfma_dups)
+    return fail(SP_EINVAL,
+                "%u connected synapses repeat a pixel of their column; the 0/1 mask of the "
+                "matrix-product mode cannot count them (use the gather mode)",
+                h->mfma_dups);
+  int32_t* ov = overlaps_dev;
+  if (!ov) {
+    int rc = infer_ov_scratch(h, num_frames, &ov);
+    if (rc) return rc;
+  }
+  // frame chunks whose word offsets stay below 2^31
+  const uint32_t fmax = (uint32_t)std::min<size_t>(num_frames, ((size_t)1 << 31) / sh.W - 1);
+  for (uint32_t f0 = 0; f0 < num_frames; f0 += fmax) {
+    const uint32_t F = std::min(fmax, num_frames - f0);
+    const uint32_t splits = htmsp::mfma_splits(sh, F, (uint32_t)h->cus);
+    const size_t need = splits > 1 ? (size_t)splits * F * sh.C : 0;
+    if (need > h->mfma_part_elems) {
+      if (h->mfma_part) {
+        e = hipFree(h->mfma_part);
+        h->mfma_part = nullptr;
+        h->mfma_part_elems = 0;
+        if (e != hipSuccess) return hip_fail(e, "partial sums free");
+      }
+      e = hipMalloc(&h->mfma_part, sizeof(int32_t) * need);
+      if (e != hipSuccess) {
+        h->mfma_part = nullptr;
+        return fail(SP_ENOMEM, "partial sums hipMalloc(%zu): %s", sizeof(int32_t) * need,
+                    hipGetErrorString(e));
+      }
+      h->mfma_part_elems = need;
+    }
+    e = htmsp::launch_infer_mfma(frames_dev + (size_t)f0 * sh.W, F, h->mfma_mask, sh, splits,
+                                 h->mfma_part, ov + (size_t)f0 * sh.C, s);
+    if (e != hipSuccess) return hip_fail(e, "matrix-product inference launch");
+  }
+  return infer_topk(h, ov, num_frames, winners_dev, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+int sp_infer(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames, int mode,
+             int32_t* overlaps_dev, int32_t* winners_dev, void* stream) {
+  int rc = check_step_args(h, frames_dev, num_frames, overlaps_dev, winners_dev);
+  if (rc) return rc;
+  if (mode != SP_INFER_GATHER && mode != SP_INFER_MFMA_I8)
+    return fail(SP_EINVAL, "unknown inference mode %d", mode);
+  if (num_frames == 0) return ok();
+  DeviceScope ds(h->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  rc = mode == SP_INFER_GATHER
+           ? infer_gather(h, frames_dev, num_frames, overlaps_dev, winners_dev, s)
+           : infer_mfma(h, frames_dev, num_frames, overlaps_dev, winners_dev, s);
+  return rc ? rc : ok();
 }
 
 int sp_step_many(sp_handle* const* hs, uint32_t n, const uint32_t* const* frames_dev,
@@ -678,15 +813,16 @@ int sp_step_many(sp_handle* const* hs, uint32_t n, const uint32_t* const* frames
     if (nact_c > 0) {
       int rc = many_launch(hs + i0, i1 - i0, frames_dev + i0, num_frames + i0, learn,
                            overlaps_dev ? overlaps_dev + i0 : nullptr, winners_dev + i0, s, dev,
-                           maxb, aligned, tiles_c, nact_c, Fmax_c, hs[0]->err);
-      if (rc) return rc;
+                           maxb, aligned, tiles_c, nact_c, Fmax_c);
+      if (rc) {
+        // the instances of this and later launches were not stepped; those of
+        // earlier launches were (their counters have moved on)
+        for (uint32_t i = i0; i < n; ++i)
+          if (num_frames[i]) hs[i]->broken = true;
+        return rc;
+      }
     }
     i0 = i1;
-  }
-  for (uint32_t i = 0; i < n; ++i) {
-    if (num_frames[i] == 0) continue;
-    hs[i]->many_steps += num_frames[i];
-    if (learn) ++hs[i]->state_version;
   }
   return ok();
 }
@@ -755,7 +891,7 @@ int sp_step_local(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames,
     return fail(SP_EINVAL, "frames (4-byte aligned) and active are required");
   DeviceScope ds(h->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (learn) ++h->state_version;
+  note_learned(h, num_frames, learn);
   if (h->lkernel) {
     htmsp::LocalArgs a;
     a.idx = h->idx;
@@ -850,7 +986,7 @@ int sp_step_boost(sp_handle* h, const sp_boost_config* bc, const uint32_t* frame
   uint8_t* raise = reinterpret_cast<uint8_t*>(boost + sh.C);
   const htmsp::BoostParams bp = {bc->period_log2, bc->min_pct_q16, bc->max_boost_q8,
                                  bc->bump_q8};
-  if (learn) ++h->state_version;
+  note_learned(h, num_frames, learn);
   if (h->bkernel) {
     htmsp::BoostArgs a;
     a.idx = h->idx;
@@ -1015,10 +1151,114 @@ int sp_destroy(sp_handle* h) {
     if (e == hipSuccess && h->infer_list) e = hipFree(h->infer_list);
     if (e == hipSuccess && h->infer_ov) e = hipFree(h->infer_ov);
     if (e == hipSuccess && h->boost_mem) e = hipFree(h->boost_mem);
+    if (e == hipSuccess && h->mfma_mask) e = hipFree(h->mfma_mask);
+    if (e == hipSuccess && h->mfma_part) e = hipFree(h->mfma_part);
     if (e != hipSuccess) rc = hip_fail(e, "destroy");
   }
   delete h;
   return rc ? rc : ok();
+}
+
+size_t sp_state_bytes(const sp_config* cfg) {
+  if (check_config(cfg)) return 0;
+  return (sizeof(uint32_t) + sizeof(float)) * (size_t)cfg->num_columns * cfg->synapses_per_column;
+}
+
+int sp_get_state(sp_handle* h, uint32_t* idx_host, float* perm_host, uint64_t* frames_seen,
+                 void* stream) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  DeviceScope ds(h->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t n = (size_t)h->sh.C * h->sh.S;
+  hipError_t e = hipSuccess;
+  if (idx_host) e = hipMemcpyAsync(idx_host, h->idx, sizeof(uint32_t) * n, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess && perm_host)
+    e = hipMemcpyAsync(perm_host, h->perm, sizeof(float) * n, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "state copy");
+  if (frames_seen) *frames_seen = h->frames_seen;
+  return ok();
+}
+
+int sp_set_state(sp_handle* h, const uint32_t* idx_host, const float* perm_host,
+                 uint64_t frames_seen, void* stream) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (!perm_host) return fail(SP_EINVAL, "perm is NULL");
+  const size_t n = (size_t)h->sh.C * h->sh.S;
+  for (size_t i = 0; idx_host && i < n; ++i)
+    if (idx_host[i] >= h->sh.N)
+      return fail(SP_EINVAL, "idx[%zu]=%u >= input_bits=%u", i, idx_host[i], h->sh.N);
+  for (size_t i = 0; i < n; ++i) {
+    const float q = perm_host[i] * 256.0f;
+    if (!(q >= 0.0f && q <= 256.0f && q == (float)(int)q))
+      return fail(SP_EINVAL, "perm[%zu]=%.9g is off the 1/256 grid or outside [0,1]", i,
+                  (double)perm_host[i]);
+  }
+  DeviceScope ds(h->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipSuccess;
+  if (idx_host) e = hipMemcpyAsync(h->idx, idx_host, sizeof(uint32_t) * n, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h->perm, perm_host, sizeof(float) * n, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    h->broken = true;
+    return hip_fail(e, "state copy");
+  }
+  ++h->state_version;
+  h->frames_seen = frames_seen;
+  return ok();
+}
+
+int sp_get_boost_state(sp_handle* h, uint32_t* active_duty_host, uint32_t* overlap_duty_host,
+                       uint32_t* boost_host, void* stream) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  DeviceScope ds(h->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  rc = ensure_boost(h, s);
+  if (rc) return rc;
+  const size_t C = h->sh.C, n = sizeof(uint32_t) * C;
+  uint32_t* dst[3] = {active_duty_host, overlap_duty_host, boost_host};
+  hipError_t e = hipSuccess;
+  for (size_t i = 0; i < 3 && e == hipSuccess; ++i)
+    if (dst[i]) e = hipMemcpyAsync(dst[i], h->boost_mem + i * C, n, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "boost state copy");
+  return ok();
+}
+
+int sp_set_boost_state(sp_handle* h, const uint32_t* active_duty_host,
+                       const uint32_t* overlap_duty_host, const uint32_t* boost_host,
+                       void* stream) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (!active_duty_host || !overlap_duty_host || !boost_host)
+    return fail(SP_EINVAL, "active duty, overlap duty and boost are all required");
+  const uint32_t C = h->sh.C;
+  for (uint32_t c = 0; c < C; ++c) {
+    if (active_duty_host[c] > 65536 || overlap_duty_host[c] > 65536)
+      return fail(SP_EINVAL, "duty cycle of column %u above 65536", c);
+    if (boost_host[c] < 256 || boost_host[c] > 4096)
+      return fail(SP_EINVAL, "boost[%u]=%u outside 256..4096", c, boost_host[c]);
+  }
+  DeviceScope ds(h->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  rc = ensure_boost(h, s);
+  if (rc) return rc;
+  const uint32_t* src[3] = {active_duty_host, overlap_duty_host, boost_host};
+  hipError_t e = hipSuccess;
+  for (size_t i = 0; i < 3 && e == hipSuccess; ++i)
+    e = hipMemcpyAsync(h->boost_mem + i * (size_t)C, src[i], sizeof(uint32_t) * C,
+                       hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    h->broken = true;
+    return hip_fail(e, "boost state copy");
+  }
+  return ok();
 }
 
 const char* sp_last_error(void) { return g_err.c_str(); }

@@ -130,6 +130,25 @@ hipError_t launch_infer_gather(uint32_t maxn, const uint32_t* frames, uint32_t F
 hipError_t launch_topk_batch(const int32_t* ov, uint32_t F, const Shape& sh, int32_t* winners,
                              hipStream_t s);
 
+// Batched inference as a dense int8 matrix product (sp_infer_mfma.hip):
+// overlaps [F][C] = frames (0/1 per pixel) x connected mask (0/1), widened
+// from bits to int8 in registers, int32 accumulation.
+// Words per row of the bit mask [C][Wm] for W words per frame.
+uint32_t mfma_mask_words(uint32_t W);
+// Builds the mask of the connected synapses (zeroing it first) and counts
+// in *dup the connected synapses of a column that repeat a pixel.
+hipError_t launch_mfma_mask(const uint32_t* idx, const float* perm, const Shape& sh,
+                            uint32_t* mask, uint32_t* dup, hipStream_t s);
+// Splits of the pixel range for F frames (partial sums [splits][F][C] when
+// above 1) on a device of `cus` compute units.
+uint32_t mfma_splits(const Shape& sh, uint32_t F, uint32_t cus);
+// Gated overlaps [F][C] into ov; `part` holds splits * F * C partial sums
+// (unused when splits == 1).  F * W and C * mfma_mask_words(W) must stay
+// below 2^31.
+hipError_t launch_infer_mfma(const uint32_t* frames, uint32_t F, const uint32_t* mask,
+                             const Shape& sh, uint32_t splits, int32_t* part, int32_t* ov,
+                             hipStream_t s);
+
 // Adaptive video encoder (sp_encode.hip).  W x H RGB input, w x h output
 // (w = W / factor, h = H / factor), `words` per encoded frame; block means
 // use area = factor^2 and area_magic = ceil(2^32 / area) (factor <= 32).
@@ -219,6 +238,9 @@ struct ManyInst {
   Shape sh;
   uint32_t F, step_base, guess;
   uint32_t smagic;         // ceil(2^32 / S), 0 for S = 1: floor(p / S) for p < 2^13
+  uint32_t* err;           // the handle's error word, set when the launch gives up
+  uint32_t stall;          // 0; a test of the failure path sets 1 (see sp_test_stall)
+  uint32_t pad;
 };
 
 struct ManyTask {
@@ -229,7 +251,7 @@ struct ManyArgs {
   ManyInst* insts;
   const ManyTask* tasks;
   const uint32_t* task_off;  // [grid + 1]: tasks of block b are [task_off[b], task_off[b+1])
-  uint32_t* err;
+  uint32_t* err;             // the launch's error word (0 at launch): every wait gives up once set
   uint32_t Fmax, learn, spin_limit, pad;
 };
 

@@ -213,6 +213,8 @@ __device__ void tile_step(const ManyArgs& a, const ManyInst& in, uint32_t c0, ui
 __device__ bool topk_try(ManyInst& in, uint32_t t, uint32_t lane) {
   const Shape& sh = in.sh;
   const uint32_t tag = (in.step_base + t + 1) & 0xFFFFu;
+  // a stalled instance (failure-path tests) waits for a tag no tile writes
+  const uint32_t want = in.stall ? (tag + 2) & 0xFFFFu : tag;
   const uint32_t nv = (sh.C + 4 * kWave - 1) / (4 * kWave);
   const HTMSP_G uint64_t* src = gbl(reinterpret_cast<const uint64_t*>(in.ovx));
   uint64_t ev[kManyNV];
@@ -222,7 +224,7 @@ __device__ bool topk_try(ManyInst& in, uint32_t t, uint32_t lane) {
   // loads of a half are in flight at once.
   auto pair_col = [&](uint32_t i) { return (i / 2) * 4 * kWave + 4 * lane + 2 * (i % 2); };
   auto fresh = [&](uint64_t r, uint32_t c) {
-    return (uint32_t)(r >> 16) % 65536u == tag && (c + 1 >= sh.C || (uint32_t)(r >> 48) == tag);
+    return (uint32_t)(r >> 16) % 65536u == want && (c + 1 >= sh.C || (uint32_t)(r >> 48) == want);
   };
   auto fold = [&](uint64_t r, uint32_t i, uint32_t c) {
     const uint64_t v = (r & 0xFFFFull) | (c + 1 < sh.C ? ((r >> 32) & 0xFFFFull) << 16 : 0ull);
@@ -320,7 +322,9 @@ __device__ bool topk_try(ManyInst& in, uint32_t t, uint32_t lane) {
 // the whole workgroup runs its step.  In a top-k workgroup every wave polls
 // its own instances (tasks j with j % 4 == wave) and resolves any whose
 // overlaps of its next step are all published.  Both loops end when every
-// task has taken all its steps, or on abort (spin limit or the error word).
+// task has taken all its steps, or on abort (spin limit or the launch's error
+// word); a workgroup that gives up also sets the error word of every instance
+// it holds a task of, so that each affected handle reports the failure.
 template <bool ALIGNED>
 __global__ __launch_bounds__(kManyThreads, 2) void k_sp_many(ManyArgs a) {
   constexpr uint32_t kSlots = kMaxTopkSlots > kMaxTileSlots ? kMaxTopkSlots : kMaxTileSlots;
@@ -367,7 +371,11 @@ __global__ __launch_bounds__(kManyThreads, 2) void k_sp_many(ManyArgs a) {
         __builtin_amdgcn_s_sleep(1);
       }
     }
-    if (fail && lane == 0) store_entry(err, 1u);
+    if (fail && lane == 0) {
+      store_entry(err, 1u);
+      // this wave's instances may be part-way through a step
+      for (uint32_t j = wave; j < nt; j += kManyThreads / kWave) store_entry(gbl(s_inst[j].err), 1u);
+    }
     return;
   }
 
@@ -417,7 +425,11 @@ __global__ __launch_bounds__(kManyThreads, 2) void k_sp_many(ManyArgs a) {
     const uint32_t status = s_pick[3];
     if (status == 1) break;
     if (status == 2) {
-      if (tid == 0) store_entry(err, 1u);
+      if (tid == 0) {
+        store_entry(err, 1u);
+        // the instances of this workgroup's tiles may be part-way through a step
+        for (uint32_t j = 0; j < nt; ++j) store_entry(gbl(s_inst[j].err), 1u);
+      }
       break;
     }
     if (status == 0) {

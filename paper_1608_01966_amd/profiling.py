@@ -33,6 +33,8 @@ KERNEL_SOURCES = {
     "k_infer_gather": ("sp_infer.hip", "sp_device.h", "sp_internal.h"),
     "k_infer_gather_db": ("sp_infer.hip", "sp_device.h", "sp_internal.h"),
     "k_topk_batch": ("sp_infer.hip", "sp_device.h", "sp_internal.h"),
+    "k_infer_mfma": ("sp_infer_mfma.hip", "sp_device.h", "sp_internal.h"),
+    "k_mfma_reduce": ("sp_infer_mfma.hip", "sp_device.h", "sp_internal.h"),
     "k_sp_many": ("sp_many.hip", "sp_device.h", "sp_internal.h"),
     "k_encode": ("sp_encode.hip", "sp_device.h", "sp_internal.h"),
     "k_zero": ("sp_encode.hip", "sp_device.h", "sp_internal.h"),

@@ -82,3 +82,26 @@ def test_null_handle_and_args_are_rejected_on_host():
     assert L.sp_create(ctypes.byref(cfg), None, None, None, ctypes.byref(out)) == sp.SP_EINVAL
     assert L.sp_create(None, None, None, None, ctypes.byref(out)) == sp.SP_EINVAL
     assert out.value is None
+
+
+def test_state_bytes_and_checkpoint_calls_without_a_handle():
+    good = synth.sp_config(518400, 1024, 256, 4, 40)
+    assert sp.sp_state_bytes(good) == 8 * 1024 * 256
+    bad = dict(good)
+    bad["num_columns"] = 0
+    assert sp.sp_state_bytes(bad) == 0
+    L = _native.lib()
+    seen = ctypes.c_uint64()
+    u32 = (ctypes.c_uint32 * 4)()
+    assert L.sp_get_state(None, None, None, ctypes.byref(seen), None) == sp.SP_EINVAL
+    assert L.sp_set_state(None, None, None, 0, None) == sp.SP_EINVAL
+    assert L.sp_get_boost_state(None, u32, u32, u32, None) == sp.SP_EINVAL
+    assert L.sp_set_boost_state(None, u32, u32, u32, None) == sp.SP_EINVAL
+    assert "NULL" in sp.sp_last_error()
+
+
+def test_inference_modes_are_distinct_constants():
+    assert sp.SP_INFER_GATHER == 0 and sp.SP_INFER_MFMA_I8 == 1
+    L = _native.lib()
+    # mode is checked after the handle: a NULL handle fails first
+    assert L.sp_infer(None, None, 0, 7, None, None, None) == sp.SP_EINVAL

@@ -66,3 +66,57 @@ def test_stall_applies_to_one_launch_only():
     assert torch.equal(win, win2) and torch.equal(ov, ov2)
     a.close()
     b.close()
+
+
+def test_many_instance_stall_marks_every_handle():
+    """One handle of a sp_step_many launch waits for entries that are never
+    written: every wait of the launch gives up and the launch drains.  The
+    stalled handle reports SP_EDEVICE on sp_sync and refuses further steps;
+    every other handle either reports SP_EDEVICE too (its steps may have been
+    cut short) or took all its steps and holds the oracle's results.  A later
+    launch over fresh handles is unaffected (the error word belongs to one
+    launch)."""
+    import torch
+    import oracle
+    ws = [synth.random_instance(60 + i, synth.sp_config(4096, 256 * (i + 1), 64, 2, 10),
+                                frames=6, density=0.2) for i in range(3)]
+
+    def step_all(pools):
+        wins = [torch.empty((6, w.cfg["winners"]), dtype=torch.int32, device="cuda") for w in ws]
+        fr = [torch.from_numpy(w.frames.view(np.int32)).cuda() for w in ws]
+        sp.sp_step_many([p.handle for p in pools], [w.cfg for w in ws], fr, True, None, wins)
+        return wins
+
+    def expect(w):
+        return oracle.run(w.cfg, w.idx, w.perm, w.frames, learn=True, want_overlaps=False)
+
+    pools = [sp.SpatialPooler(w.cfg, w.idx, w.perm) for w in ws]
+    sp.sp_test_stall(pools[1].handle, 200)
+    wins = step_all(pools)
+    torch.cuda.synchronize()
+    for i, (p, w, wn) in enumerate(zip(pools, ws, wins)):
+        try:
+            p.sync()
+        except sp.SpError as e:
+            assert e.code == sp.SP_EDEVICE
+            with pytest.raises(sp.SpError) as e2:
+                sp.sp_step(p.handle, w.cfg, torch.from_numpy(w.frames.view(np.int32)).cuda(),
+                           True, None, torch.empty((6, w.cfg["winners"]), dtype=torch.int32,
+                                                   device="cuda"))
+            assert e2.value.code == sp.SP_EBROKEN
+            continue
+        assert i != 1, "the stalled handle reported no failure"
+        _, e_win, e_perm = expect(w)
+        assert np.array_equal(wn.cpu().numpy(), e_win), i
+        assert np.array_equal(p.perm.cpu().numpy().astype(np.float64), e_perm), i
+    for p in pools:
+        p.close()
+    fresh = [sp.SpatialPooler(w.cfg, w.idx, w.perm) for w in ws]
+    wins = step_all(fresh)
+    for p in fresh:
+        p.sync()
+    for w, wn in zip(ws, wins):
+        _, e_win, _ = expect(w)
+        assert np.array_equal(wn.cpu().numpy(), e_win)
+    for p in fresh:
+        p.close()

@@ -161,6 +161,22 @@ int sp_step_plain(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames,
 int sp_infer(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames, int mode,
              int32_t* overlaps_dev, int32_t* winners_dev, void* stream);
 
+/* Batched inference that allocates nothing, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): the gather mode of sp_infer with the
+ * same results, its working lists held in a fixed device scratch array of
+ * sp_infer_noalloc_max_bytes() (16 MiB) per GPU that the library keeps for
+ * the life of the process, instead of lists the handle allocates.  The
+ * caller passes every input and output: overlaps_dev [F][C] is required.
+ * The lists are rebuilt by every call (no state version is kept, and the
+ * stream is never synchronised).  SP_EINVAL if S > 256 or if the lists,
+ * 4 (S C + C) bytes, exceed the scratch.  All calls on one GPU share its
+ * scratch: calls that overlap in time on one GPU (on different streams, or
+ * from different threads) race and give wrong results. */
+size_t sp_infer_noalloc_max_bytes(void);
+int sp_infer_noalloc(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames,
+                     int32_t* overlaps_dev, int32_t* winners_dev, void* stream);
+
 /* Steps n independent handles together (each handle as by sp_step: its
  * frames in order, overlap, inhibition and, when learn != 0, learning) in one
  * persistent launch whose workgroups serve tiles of every instance and one

@@ -70,6 +70,8 @@ SIGNATURES = [
     ("sp_step", ctypes.c_int, [P, P, U32, ctypes.c_int, P, P, P]),
     ("sp_step_plain", ctypes.c_int, [P, P, U32, ctypes.c_int, P, P, P]),
     ("sp_infer", ctypes.c_int, [P, P, U32, ctypes.c_int, P, P, P]),
+    ("sp_infer_noalloc_max_bytes", ctypes.c_size_t, []),
+    ("sp_infer_noalloc", ctypes.c_int, [P, P, U32, P, P, P]),
     ("sp_step_many", ctypes.c_int, [P, U32, P, P, ctypes.c_int, P, P, P]),
     ("sp_set_histogram", ctypes.c_int, [P, P]),
     ("sp_step_boost", ctypes.c_int, [P, ctypes.POINTER(BoostCfg), P, U32, ctypes.c_int, P, P,

@@ -749,6 +749,71 @@ int sp_infer(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames, int 
   return rc ? rc : ok();
 }
 
+}  // extern "C"
+
+namespace {
+
+// Scratch of sp_infer_noalloc: the compacted connected lists (slot-major
+// [S][C], then counts [C]) of the handle being served.  Each GPU the library
+// runs on holds its own copy for the life of the process; host code uses
+// only the address hipGetSymbolAddress returns for the current device.
+constexpr size_t kNoAllocScratchBytes = size_t(16) << 20;
+__device__ __align__(256) uint32_t scratch[kNoAllocScratchBytes / sizeof(uint32_t)];
+
+std::mutex g_scratch_mu;
+uint32_t* g_scratch[16];
+
+// The device address of this device's scratch, looked up once per device.
+int noalloc_scratch(int device, uint32_t** out) {
+  if (device < 0 || device >= 16) return fail(SP_EDEVICE, "device %d out of range", device);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[device]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "scratch address");
+    if (!ptr) return fail(SP_EDEVICE, "scratch address is NULL");
+    g_scratch[device] = static_cast<uint32_t*>(ptr);
+  }
+  *out = g_scratch[device];
+  return SP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t sp_infer_noalloc_max_bytes(void) { return kNoAllocScratchBytes; }
+
+int sp_infer_noalloc(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames,
+                     int32_t* overlaps_dev, int32_t* winners_dev, void* stream) {
+  int rc = check_step_args(h, frames_dev, num_frames, overlaps_dev, winners_dev);
+  if (rc) return rc;
+  if (num_frames && !overlaps_dev) return fail(SP_EINVAL, "overlaps is NULL");
+  const Shape& sh = h->sh;
+  if (sh.S > htmsp::infer_max_list())
+    return fail(SP_EINVAL, "synapses_per_column=%u > %u: a list could outgrow the gather registers",
+                sh.S, htmsp::infer_max_list());
+  const size_t need = sizeof(uint32_t) * ((size_t)sh.S * sh.C + sh.C);
+  if (need > kNoAllocScratchBytes)
+    return fail(SP_EINVAL, "the lists need %zu bytes; the scratch holds %zu", need,
+                kNoAllocScratchBytes);
+  if (num_frames == 0) return ok();
+  DeviceScope ds(h->device);
+  uint32_t* list = nullptr;
+  rc = noalloc_scratch(h->device, &list);
+  if (rc) return rc;
+  uint32_t* cnt = list + (size_t)sh.S * sh.C;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // every slot and count is rewritten, so nothing has to start at zero
+  hipError_t e = htmsp::launch_infer_prep(h->idx, h->perm, sh, list, cnt, nullptr, s);
+  if (e == hipSuccess)
+    e = htmsp::launch_infer_gather(sh.S, frames_dev, num_frames, list, cnt, sh, overlaps_dev,
+                                   (uint32_t)h->cus, s);
+  if (e != hipSuccess) return hip_fail(e, "inference launch");
+  rc = infer_topk(h, overlaps_dev, num_frames, winners_dev, s);
+  return rc ? rc : ok();
+}
+
 int sp_step_many(sp_handle* const* hs, uint32_t n, const uint32_t* const* frames_dev,
                  const uint32_t* num_frames, int learn, int32_t* const* overlaps_dev,
                  int32_t* const* winners_dev, void* stream) {

@@ -52,7 +52,7 @@ __global__ __launch_bounds__(256) void k_infer_prep(const uint32_t* __restrict__
   }
   cnt[c] = n;
   for (uint32_t i = n; i < sh.S; ++i) list[(size_t)i * sh.C + c] = pad;
-  atomicMax(maxcnt, n);
+  if (maxcnt) atomicMax(maxcnt, n);
 }
 
 // Gather overlaps.  Block b serves column block cb (kInferThreads columns)
@@ -322,8 +322,10 @@ size_t infer_lds_limit() { return 65536; }
 
 hipError_t launch_infer_prep(const uint32_t* idx, const float* perm, const Shape& sh,
                              uint32_t* list, uint32_t* cnt, uint32_t* maxcnt, hipStream_t s) {
-  hipError_t e = hipMemsetAsync(maxcnt, 0, sizeof(uint32_t), s);
-  if (e != hipSuccess) return e;
+  if (maxcnt) {
+    hipError_t e = hipMemsetAsync(maxcnt, 0, sizeof(uint32_t), s);
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(k_infer_prep, dim3((sh.C + 255) / 256), dim3(256), 0, s, idx, perm, sh,
                      sh.W << 7, list, cnt, maxcnt);
   return hipGetLastError();

@@ -118,7 +118,8 @@ hipError_t launch_learn_plain(const uint32_t* idx, float* perm, const uint32_t* 
 // Longest connected list the register-resident gather kernel holds.
 uint32_t infer_max_list();
 // Compacts every column's connected inputs into list [S][C] (slot-major,
-// padded with a pixel whose word is zero), counts in cnt [C], max in *maxcnt.
+// padded with a pixel whose word is zero), counts in cnt [C], max in *maxcnt
+// (maxcnt null: not counted, and nothing is cleared).
 hipError_t launch_infer_prep(const uint32_t* idx, const float* perm, const Shape& sh,
                              uint32_t* list, uint32_t* cnt, uint32_t* maxcnt, hipStream_t s);
 // Overlaps [F][C] of F frames from the compacted lists (maxn <= infer_max_list()).

@@ -137,9 +137,11 @@ int sp_step_plain(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames,
  *
  * mode SP_INFER_GATHER compacts every column's connected synapses once per
  * state change (a step that learned, or sp_check_state), then counts active
- * inputs by gathering bits of each frame staged in LDS.  The first call
- * after a state change synchronises `stream` (it reads back the longest
- * connected list); SP_EINVAL if that list exceeds 256 synapses.
+ * inputs by gathering bits of each frame staged in LDS, each column's list
+ * held in registers.  The first call after a state change synchronises
+ * `stream` (it reads back the longest connected list); when that list is
+ * longer than 256 synapses the lists are read from device memory for every
+ * frame instead (same results, slower).
  *
  * mode SP_INFER_MFMA_I8 computes the overlaps as one dense matrix product,
  * frames (0/1 per pixel) times the connected mask (1 where a connected
@@ -292,8 +294,9 @@ int sp_inhibit_local(const int32_t* overlaps_dev, uint32_t num_frames, uint32_t 
  * where the shape allows it (C <= 4096, S <= 1024, see
  * sp_step_local_kernel), else one launch sequence per frame; the results
  * are the same.  overlaps_dev [F][C] may be NULL; active_dev is [F][C]
- * uint8.  The handle's histogram, if set, is not updated by this call.  A
- * device-side failure of the persistent launch is reported by sp_sync. */
+ * uint8.  The handle's histogram, if set, gains 1 per frame for each
+ * active column.  A device-side failure of the persistent launch is
+ * reported by sp_sync. */
 int sp_step_local(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames, int learn,
                   uint32_t grid_w, uint32_t radius, int32_t* overlaps_dev, uint8_t* active_dev,
                   void* stream);
@@ -331,9 +334,10 @@ int sp_encode(const sp_encoder_config* cfg, const uint8_t* rgb_dev, uint32_t num
 /* Per-stream SDR histogram (Section 2: the pooler output of every frame of a
  * video is accumulated into a histogram, the video's feature vector).
  * hist_dev: caller-owned uint32 [num_columns] device buffer, or NULL to stop.
- * From then on every sp_step, sp_step_plain, sp_infer and sp_step_many of
- * this handle adds, for each frame, 1 to hist_dev[c] for each winner c, on
- * the call's stream after its winners are written.  The library never clears
+ * From then on every sp_step, sp_step_plain, sp_infer, sp_infer_noalloc,
+ * sp_step_many, sp_step_boost and sp_step_local of this handle adds, for
+ * each frame, 1 to hist_dev[c] for each winner (for sp_step_local: each
+ * active column) c, on the call's stream after its outputs are written.  The library never clears
  * it; the buffer must outlive its use.  SP_EINVAL on a bad handle or a
  * misaligned pointer. */
 int sp_set_histogram(sp_handle* h, uint32_t* hist_dev);

@@ -27,8 +27,9 @@ def build() -> str:
     os.makedirs(os.path.dirname(_LIB_PATH), exist_ok=True)
     tmp = _LIB_PATH + ".tmp"
     subprocess.check_call([
-        "gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-Werror", "-fPIC", "-shared",
-        os.path.join(_HERE, "sp_oracle.c"), os.path.join(_HERE, "enc_oracle.c"), "-o", tmp,
+        "gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-Werror", "-fPIC", "-shared", "-pthread",
+        os.path.join(_HERE, "sp_oracle.c"), os.path.join(_HERE, "sp_oracle_mt.c"),
+        os.path.join(_HERE, "enc_oracle.c"), "-o", tmp,
     ])
     os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -84,6 +85,9 @@ def _load():
         lib.spo_learn.restype = None
         lib.spo_run.argtypes = [ctypes.POINTER(_Cfg), P, P, P, ctypes.c_uint32, ctypes.c_int, P, P]
         lib.spo_run.restype = ctypes.c_int
+        lib.spo_run_threads.argtypes = [ctypes.POINTER(_Cfg), P, P, P, ctypes.c_uint32,
+                                        ctypes.c_int, P, P, ctypes.c_uint32]
+        lib.spo_run_threads.restype = ctypes.c_int
         lib.spo_histogram.argtypes = [P, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, P]
         lib.spo_histogram.restype = ctypes.c_int
         lib.spo_run_boost.argtypes = [ctypes.POINTER(_Cfg), ctypes.POINTER(_Boost), P, P, P,
@@ -179,6 +183,28 @@ def run(cfg: dict, idx: np.ndarray, perm: np.ndarray, frames: np.ndarray, learn:
     c = _cfg(cfg)
     rc = _load().spo_run(ctypes.byref(c), _ptr(idx), _ptr(perm), _ptr(frames), F, int(bool(learn)),
                          _ptr(ov) if ov is not None else None, _ptr(win))
+    if rc != 0:
+        raise ValueError("oracle rejected its arguments")
+    return ov, win, perm
+
+
+def run_threads(cfg: dict, idx: np.ndarray, perm: np.ndarray, frames: np.ndarray,
+                threads: int, learn: bool = True, want_overlaps: bool = True):
+    """``run`` on `threads` host threads (same results): per frame the
+    overlap and the learning split by column ranges, the inhibition on one
+    thread."""
+    idx = np.ascontiguousarray(idx, dtype=np.uint32)
+    perm = np.array(perm, dtype=np.float64, order="C", copy=True)
+    frames = np.ascontiguousarray(frames, dtype=np.uint32)
+    F = frames.shape[0] if frames.ndim == 2 else (0 if frames.size == 0 else 1)
+    frames = frames.reshape(F, _words(cfg)) if F else frames.reshape(0, _words(cfg))
+    C, k = int(cfg["num_columns"]), int(cfg["winners"])
+    ov = np.zeros((F, C), dtype=np.int32) if want_overlaps else None
+    win = np.zeros((F, k), dtype=np.int32)
+    c = _cfg(cfg)
+    rc = _load().spo_run_threads(ctypes.byref(c), _ptr(idx), _ptr(perm), _ptr(frames), F,
+                                 int(bool(learn)), _ptr(ov) if ov is not None else None,
+                                 _ptr(win), int(threads))
     if rc != 0:
         raise ValueError("oracle rejected its arguments")
     return ov, win, perm

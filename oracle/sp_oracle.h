@@ -135,6 +135,13 @@ int spo_run_boost(const spo_config* cfg, const spo_boost* bc, const uint32_t* id
  * feature vector).  For every frame t < num_frames and every entry
  * c = winners[t][j] >= 0, adds 1 to hist[c]; hist[C] is not cleared first.
  * Returns 0, or -1 on an entry >= C. */
+/* spo_run on `threads` host threads (1..1024), with the same results: the
+ * overlap and the learning of each frame split by contiguous column ranges,
+ * the inhibition on one thread (sp_oracle_mt.c). */
+int spo_run_threads(const spo_config* cfg, const uint32_t* idx, double* perm,
+                    const uint32_t* frames, uint32_t num_frames, int learn, int32_t* overlaps,
+                    int32_t* winners, uint32_t threads);
+
 int spo_histogram(const int32_t* winners, uint32_t num_frames, uint32_t k, uint32_t C,
                   uint32_t* hist);
 

@@ -26,7 +26,7 @@ from ._native import (SP_EBROKEN, SP_EDEVICE, SP_EINVAL, SP_ENOMEM, SP_INFER_GAT
 __all__ = [
     "SpError", "SpatialPooler", "synth", "sp_config_check", "sp_frame_words",
     "sp_workspace_bytes", "sp_check_state_host", "sp_create", "sp_check_state", "sp_step",
-    "sp_step_plain", "sp_infer", "sp_step_many", "sp_set_histogram", "sp_encode",
+    "sp_step_plain", "sp_infer", "sp_step_many", "sp_step_many_raw", "sp_set_histogram", "sp_encode",
     "sp_inhibit_local", "sp_step_local", "sp_step_boost", "sp_boost_state", "sp_boost_reset",
     "sp_encoded_bits", "sp_step_is_persistent", "sp_step_kernel", "sp_step_local_kernel",
     "sp_step_boost_kernel", "sp_test_stall", "STEP_KERNELS", "sp_state_bytes", "sp_get_state",
@@ -181,6 +181,29 @@ def sp_step_many(handles, cfgs, frames, learn: bool, overlaps, winners, stream=N
            "sp_step_many")
 
 
+def sp_step_many_raw(handles: np.ndarray, frames: np.ndarray, num_frames: np.ndarray,
+                     learn: bool, overlaps, winners: np.ndarray, stream=None) -> None:
+    """sp_step_many with its arrays already built: handles, frames and
+    winners are uint64 numpy arrays of handles and device addresses,
+    num_frames a uint32 array, overlaps a uint64 array or None (marshalling
+    only, for schedulers that batch hundreds of handles per call)."""
+    n = len(handles)
+    arrs = [np.ascontiguousarray(handles, dtype=np.uint64),
+            np.ascontiguousarray(frames, dtype=np.uint64),
+            np.ascontiguousarray(num_frames, dtype=np.uint32),
+            np.ascontiguousarray(winners, dtype=np.uint64)]
+    if any(len(a) != n for a in arrs[1:]):
+        raise ValueError("handles, frames, num_frames and winners must have one entry each")
+    ov = None
+    if overlaps is not None:
+        ov = np.ascontiguousarray(overlaps, dtype=np.uint64)
+        if len(ov) != n:
+            raise ValueError("overlaps must have one entry per handle")
+    _check(lib().sp_step_many(_host_ptr(arrs[0]), n, _host_ptr(arrs[1]), _host_ptr(arrs[2]),
+                              int(bool(learn)), _host_ptr(ov) if ov is not None else None,
+                              _host_ptr(arrs[3]), _stream(stream)), "sp_step_many")
+
+
 def _boost_cfg(b: dict):
     return _native.BoostCfg(int(b["period_log2"]), int(b["min_pct_q16"]),
                             int(b["max_boost_q8"]), int(b["bump_q8"]))
@@ -322,15 +345,17 @@ def sp_state_bytes(cfg) -> int:
     return int(lib().sp_state_bytes(ctypes.byref(c)))
 
 
-def sp_get_state(h: int, cfg, stream=None):
-    """(idx uint32 [C][S], perm float32 [C][S], frames_seen) in host memory."""
+def sp_get_state(h: int, cfg, stream=None, with_idx: bool = True):
+    """(idx uint32 [C][S] or None, perm float32 [C][S], frames_seen) in host
+    memory."""
     c = _cfg(cfg)
     shape = (c.num_columns, c.synapses_per_column)
-    idx = np.empty(shape, dtype=np.uint32)
+    idx = np.empty(shape, dtype=np.uint32) if with_idx else None
     perm = np.empty(shape, dtype=np.float32)
     seen = ctypes.c_uint64()
-    _check(lib().sp_get_state(ctypes.c_void_p(h), _host_ptr(idx), _host_ptr(perm),
-                              ctypes.byref(seen), _stream(stream)), "sp_get_state")
+    _check(lib().sp_get_state(ctypes.c_void_p(h), _host_ptr(idx) if with_idx else None,
+                              _host_ptr(perm), ctypes.byref(seen), _stream(stream)),
+           "sp_get_state")
     return idx, perm, int(seen.value)
 
 
@@ -373,6 +398,20 @@ def sp_sync(h: int, stream=None) -> None:
 
 def sp_destroy(h: int) -> None:
     _check(lib().sp_destroy(ctypes.c_void_p(h) if h else None), "sp_destroy")
+
+
+def _keep_for(stream, *tensors) -> None:
+    """Tensors allocated on the current stream but used by a call enqueued on
+    another `stream`: the caching allocator must not hand their memory to new
+    work before that stream has passed the call."""
+    import torch
+    if stream is None or not isinstance(stream, torch.cuda.Stream):
+        return
+    if stream == torch.cuda.current_stream(stream.device):
+        return
+    for t in tensors:
+        if t is not None:
+            t.record_stream(stream)
 
 
 class SpatialPooler:
@@ -432,6 +471,7 @@ class SpatialPooler:
         win = torch.empty((F, self.cfg["winners"]), dtype=torch.int32, device=self.idx.device)
         fn = sp_step_plain if plain else sp_step
         fn(self.handle, self.cfg, frames, learn, ov, win, stream)
+        _keep_for(stream, frames, ov, win)
         return ov, win
 
     def infer(self, frames, overlaps: bool = True, mode: int = SP_INFER_GATHER, stream=None):
@@ -446,11 +486,12 @@ class SpatialPooler:
                          device=self.idx.device) if overlaps else None
         win = torch.empty((F, self.cfg["winners"]), dtype=torch.int32, device=self.idx.device)
         sp_infer(self.handle, self.cfg, frames, mode, ov, win, stream)
+        _keep_for(stream, frames, ov, win)
         return ov, win
 
-    def get_state(self, stream=None):
-        """Checkpoint: (idx, perm, frames_seen) in host memory."""
-        return sp_get_state(self.handle, self.cfg, stream)
+    def get_state(self, stream=None, with_idx: bool = True):
+        """Checkpoint: (idx or None, perm, frames_seen) in host memory."""
+        return sp_get_state(self.handle, self.cfg, stream, with_idx)
 
     def set_state(self, idx, perm, frames_seen: int = 0, stream=None) -> None:
         """Resume from a checkpoint taken by get_state (idx None keeps the pools)."""

@@ -72,6 +72,14 @@ struct sp_handle {
   uint32_t mfma_dups;
   int32_t* mfma_part;
   size_t mfma_part_elems;
+  // Completion of the handle's last enqueued work: `idle` is recorded after
+  // every call that enqueues work on the handle (except sp_step_many, whose
+  // launches are tracked by their sequence number and staging slot), so
+  // sp_destroy waits for that work only, not for the whole device.
+  hipEvent_t idle;
+  bool idle_used;
+  uint64_t many_seq;  // sequence number of its last many-instance launch (0: none)
+  int many_slot;      // staging slot that launch used
 };
 
 namespace {
@@ -175,6 +183,17 @@ int check_handle(const sp_handle* h) {
   return SP_OK;
 }
 
+// Records, when a call returns, the completion of whatever it enqueued on
+// `s` for the handle (also when it fails part-way, so that sp_destroy still
+// waits for the launches that did go out).
+struct IdleOnExit {
+  sp_handle* h;
+  hipStream_t s;
+  ~IdleOnExit() {
+    if (h && hipEventRecord(h->idle, s) == hipSuccess) h->idle_used = true;
+  }
+};
+
 // A call that learned on F frames changed the state: batched inference
 // rebuilds what it derives from it, and the frame count moves on.
 void note_learned(sp_handle* h, uint32_t F, int learn) {
@@ -199,6 +218,14 @@ int check_step_args(const sp_handle* h, const uint32_t* frames, uint32_t F, int3
 int add_histogram(const sp_handle* h, const int32_t* winners, uint32_t F, hipStream_t s) {
   if (!h->hist || F == 0) return ok();
   hipError_t e = htmsp::launch_hist_add(winners, (size_t)F * h->sh.k, h->sh.C, h->hist, s);
+  if (e != hipSuccess) return hip_fail(e, "histogram launch");
+  return ok();
+}
+
+// The active columns of a local-inhibition call added to the histogram.
+int add_histogram_active(const sp_handle* h, const uint8_t* active, uint32_t F, hipStream_t s) {
+  if (!h->hist || F == 0) return ok();
+  hipError_t e = htmsp::launch_hist_add_active(active, F, h->sh.C, h->hist, s);
   if (e != hipSuccess) return hip_fail(e, "histogram launch");
   return ok();
 }
@@ -302,15 +329,20 @@ struct ManyCtx {
   int device = -1;
   ManySlot slot[2];
   int next = 0;
+  // launches enqueued so far; launch n reuses the slot of launch n - 2 only
+  // after that launch's completion event, so every launch numbered at most
+  // seq - 2 is known to be complete
+  uint64_t seq = 0;
 };
 
 std::mutex g_many_mu;
 ManyCtx g_many[16];
 
-int many_slot(int device, size_t bytes, ManySlot** out) {
+int many_slot(int device, size_t bytes, ManySlot** out, int* index) {
   if (device < 0 || device >= 16) return fail(SP_EDEVICE, "device %d out of range", device);
   ManyCtx& ctx = g_many[device];
   ctx.device = device;
+  *index = ctx.next;
   ManySlot& sl = ctx.slot[ctx.next];
   ctx.next ^= 1;
   hipError_t e = hipSuccess;
@@ -340,6 +372,63 @@ int many_slot(int device, size_t bytes, ManySlot** out) {
   return SP_OK;
 }
 
+// Waits for the handle's last many-instance launch, unless the library has
+// already waited for it (two launches later, when its staging slot was
+// reused).
+hipError_t many_wait(const sp_handle* h) {
+  if (!h->many_seq || h->device < 0 || h->device >= 16) return hipSuccess;
+  std::lock_guard<std::mutex> lock(g_many_mu);
+  const ManyCtx& ctx = g_many[h->device];
+  if (h->many_seq + 2 <= ctx.seq) return hipSuccess;
+  return hipEventSynchronize(ctx.slot[h->many_slot].done);
+}
+
+// Workspaces of destroyed handles, per device, for later sp_create calls: a
+// handle's workspace goes back here instead of to hipFree, which would wait
+// for every stream of the device (a serving loop that retires a stream must
+// not drain the batches in flight).  Pooled buffers are idle (sp_destroy
+// waited for their handle's work) and are cleared again on reuse; the pool
+// keeps at most kWsPoolMax bytes per device until the process ends.
+constexpr size_t kWsPoolMax = size_t(256) << 20;
+
+struct WsPool {
+  std::vector<std::pair<size_t, void*>> free;
+  size_t bytes = 0;
+};
+
+std::mutex g_ws_mu;
+WsPool g_ws[16];
+
+// A pooled workspace of at least `bytes` (at most twice that), or null.
+void* ws_take(int device, size_t bytes, size_t* got) {
+  if (device < 0 || device >= 16) return nullptr;
+  std::lock_guard<std::mutex> lock(g_ws_mu);
+  WsPool& p = g_ws[device];
+  size_t best = p.free.size();
+  for (size_t i = 0; i < p.free.size(); ++i)
+    if (p.free[i].first >= bytes && p.free[i].first <= 2 * bytes &&
+        (best == p.free.size() || p.free[i].first < p.free[best].first))
+      best = i;
+  if (best == p.free.size()) return nullptr;
+  void* ws = p.free[best].second;
+  *got = p.free[best].first;
+  p.bytes -= *got;
+  p.free.erase(p.free.begin() + (ptrdiff_t)best);
+  return ws;
+}
+
+// Returns an idle workspace to the pool; false if the pool is full (the
+// caller frees it).
+bool ws_give(int device, void* ws, size_t bytes) {
+  if (device < 0 || device >= 16) return false;
+  std::lock_guard<std::mutex> lock(g_ws_mu);
+  WsPool& p = g_ws[device];
+  if (p.bytes + bytes > kWsPoolMax) return false;
+  p.free.emplace_back(bytes, ws);
+  p.bytes += bytes;
+  return true;
+}
+
 // One cooperative launch over hs[0..n) (instances with frames; the caller
 // holds g_many_mu).  The first workgroups hold tile tasks only, dealt
 // round-robin, at most kMaxTileSlots each; the last many_topk_blocks()
@@ -352,10 +441,15 @@ int many_launch(sp_handle* const* hs, uint32_t n, const uint32_t* const* frames_
   const uint32_t kblocks = htmsp::many_topk_blocks(nact, (size_t)maxb);
   const uint32_t tblocks = (uint32_t)std::min<size_t>(ntiles, (size_t)maxb - kblocks);
   const uint32_t grid = tblocks + kblocks;
-  std::vector<std::vector<htmsp::ManyTask>> per(grid);
-  std::vector<htmsp::ManyInst> insts;
+  // tiles in instance order; tile j goes to workgroup j % tblocks, the top-k
+  // task of instance i to workgroup tblocks + i % kblocks
+  thread_local std::vector<htmsp::ManyTask> tiles;
+  thread_local std::vector<htmsp::ManyInst> insts;
+  tiles.clear();
+  insts.clear();
+  tiles.reserve(ntiles);
   insts.reserve(nact);
-  uint32_t next_tile = 0, next_topk = 0, spin_limit = kSpinLimit;
+  uint32_t spin_limit = kSpinLimit;
   for (uint32_t i = 0; i < n; ++i) {
     sp_handle* h = hs[i];
     if (num_frames[i] == 0) continue;
@@ -382,10 +476,8 @@ int many_launch(sp_handle* const* hs, uint32_t n, const uint32_t* const* frames_
     insts.push_back(in);
     const uint32_t ct = htmsp::many_tile_columns(h->sh.S);
     for (uint32_t c0 = 0; c0 < h->sh.C; c0 += ct)
-      per[next_tile++ % tblocks].push_back({id, 0u, c0, std::min(h->sh.C, c0 + ct)});
+      tiles.push_back({id, 0u, c0, std::min(h->sh.C, c0 + ct)});
   }
-  for (uint32_t id = 0; id < insts.size(); ++id)
-    per[tblocks + (next_topk++ % kblocks)].push_back({id, 1u, 0u, 0u});
 
   // staging layout: the launch's error word (cleared by the upload), the
   // instance descriptors, the tasks, the per-workgroup task offsets
@@ -394,7 +486,8 @@ int many_launch(sp_handle* const* hs, uint32_t n, const uint32_t* const* frames_
   const size_t b_tasks = align_up(sizeof(htmsp::ManyTask) * ntasks, 256);
   const size_t b_off = sizeof(uint32_t) * (grid + 1);
   ManySlot* sl = nullptr;
-  int rc = many_slot(dev, b_err + b_insts + b_tasks + b_off, &sl);
+  int slot_index = 0;
+  int rc = many_slot(dev, b_err + b_insts + b_tasks + b_off, &sl, &slot_index);
   if (rc) return rc;
   char* hb = static_cast<char*>(sl->host);
   char* db = static_cast<char*>(sl->dev);
@@ -404,9 +497,13 @@ int many_launch(sp_handle* const* hs, uint32_t n, const uint32_t* const* frames_
   htmsp::ManyTask* ht = reinterpret_cast<htmsp::ManyTask*>(hb + b_insts);
   uint32_t* hoff = reinterpret_cast<uint32_t*>(hb + b_insts + b_tasks);
   uint32_t k = 0;
-  for (uint32_t b = 0; b < grid; ++b) {
+  for (uint32_t b = 0; b < tblocks; ++b) {
     hoff[b] = k;
-    for (const auto& t : per[b]) ht[k++] = t;
+    for (size_t j = b; j < tiles.size(); j += tblocks) ht[k++] = tiles[j];
+  }
+  for (uint32_t b = 0; b < kblocks; ++b) {
+    hoff[tblocks + b] = k;
+    for (uint32_t id = b; id < insts.size(); id += kblocks) ht[k++] = {id, 1u, 0u, 0u};
   }
   hoff[grid] = k;
   hipError_t e = hipMemcpyAsync(db, hb - b_err, b_err + b_insts + b_tasks + b_off,
@@ -425,10 +522,13 @@ int many_launch(sp_handle* const* hs, uint32_t n, const uint32_t* const* frames_
   if (e == hipSuccess) e = hipEventRecord(sl->done, s);
   if (e != hipSuccess) return hip_fail(e, "many-instance launch");
   // the launch is enqueued: every instance it holds has moved on
+  const uint64_t seq = ++g_many[dev].seq;
   for (uint32_t i = 0; i < n; ++i) {
     if (num_frames[i] == 0) continue;
     hs[i]->many_steps += num_frames[i];
     hs[i]->stall_spins = 0;
+    hs[i]->many_seq = seq;
+    hs[i]->many_slot = slot_index;
     note_learned(hs[i], num_frames[i], learn);
   }
   return SP_OK;
@@ -491,10 +591,20 @@ int sp_create(const sp_config* cfg, uint32_t* idx_dev, float* perm_dev, void* st
   h->device = dev;
   const WsLayout l = ws_layout(*cfg);
   h->ws_bytes = l.total;
-  e = hipMalloc(&h->ws, l.total);
+  h->ws = ws_take(dev, l.total, &h->ws_bytes);
+  if (!h->ws) {
+    h->ws_bytes = l.total;
+    e = hipMalloc(&h->ws, l.total);
+    if (e != hipSuccess) {
+      delete h;
+      return fail(SP_ENOMEM, "workspace hipMalloc(%zu): %s", l.total, hipGetErrorString(e));
+    }
+  }
+  e = hipEventCreateWithFlags(&h->idle, hipEventDisableTiming);
   if (e != hipSuccess) {
+    if (!ws_give(dev, h->ws, h->ws_bytes)) (void)hipFree(h->ws);
     delete h;
-    return fail(SP_ENOMEM, "workspace hipMalloc(%zu): %s", l.total, hipGetErrorString(e));
+    return hip_fail(e, "completion event");
   }
   char* base = static_cast<char*>(h->ws);
   h->xchg = reinterpret_cast<uint32_t*>(base + l.xchg);
@@ -504,15 +614,13 @@ int sp_create(const sp_config* cfg, uint32_t* idx_dev, float* perm_dev, void* st
   h->many_ovx = reinterpret_cast<uint32_t*>(base + l.many_ovx);
   h->many_dec = reinterpret_cast<uint64_t*>(base + l.many_dec);
   h->xloc = reinterpret_cast<uint64_t*>(base + l.xloc);
-  e = hipMemsetAsync(h->ws, 0, l.total, s);
-  if (e != hipSuccess) {
-    (void)hipFree(h->ws);
-    delete h;
-    return hip_fail(e, "workspace clear");
-  }
-  rc = run_check_state(h, s);
+  // (run_check_state synchronises `s`, so the workspace is clear and idle
+  // when it goes back to the pool on a failure)
+  e = hipMemsetAsync(h->ws, 0, h->ws_bytes, s);
+  rc = e != hipSuccess ? hip_fail(e, "workspace clear") : run_check_state(h, s);
   if (rc) {
-    (void)hipFree(h->ws);
+    if (e != hipSuccess || !ws_give(dev, h->ws, h->ws_bytes)) (void)hipFree(h->ws);
+    (void)hipEventDestroy(h->idle);
     delete h;
     return rc;
   }
@@ -539,6 +647,7 @@ int sp_step_plain(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames,
   if (rc) return rc;
   DeviceScope ds(h->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
+  IdleOnExit idle{h, s};
   const Shape& sh = h->sh;
   note_learned(h, num_frames, learn);
   for (uint32_t t = 0; t < num_frames; ++t) {
@@ -561,6 +670,7 @@ int sp_step(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames, int l
   if (!h->persistent)
     return sp_step_plain(h, frames_dev, num_frames, learn, overlaps_dev, winners_dev, stream);
   DeviceScope ds(h->device);
+  IdleOnExit idle{h, static_cast<hipStream_t>(stream)};
   htmsp::PersistArgs a;
   a.idx = h->idx;
   a.perm = h->perm;
@@ -647,9 +757,6 @@ int infer_gather(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames,
     h->infer_maxn = maxn;
     h->infer_version = h->state_version;
   }
-  if (h->infer_maxn > htmsp::infer_max_list())
-    return fail(SP_EINVAL, "a column has %u connected synapses; batched inference holds at most %u",
-                h->infer_maxn, htmsp::infer_max_list());
   int32_t* ov = overlaps_dev;
   if (!ov) {
     int rc = infer_ov_scratch(h, num_frames, &ov);
@@ -743,6 +850,7 @@ int sp_infer(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames, int 
   if (num_frames == 0) return ok();
   DeviceScope ds(h->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
+  IdleOnExit idle{h, s};
   rc = mode == SP_INFER_GATHER
            ? infer_gather(h, frames_dev, num_frames, overlaps_dev, winners_dev, s)
            : infer_mfma(h, frames_dev, num_frames, overlaps_dev, winners_dev, s);
@@ -804,6 +912,7 @@ int sp_infer_noalloc(sp_handle* h, const uint32_t* frames_dev, uint32_t num_fram
   if (rc) return rc;
   uint32_t* cnt = list + (size_t)sh.S * sh.C;
   hipStream_t s = static_cast<hipStream_t>(stream);
+  IdleOnExit idle{h, s};
   // every slot and count is rewritten, so nothing has to start at zero
   hipError_t e = htmsp::launch_infer_prep(h->idx, h->perm, sh, list, cnt, nullptr, s);
   if (e == hipSuccess)
@@ -956,6 +1065,7 @@ int sp_step_local(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames,
     return fail(SP_EINVAL, "frames (4-byte aligned) and active are required");
   DeviceScope ds(h->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
+  IdleOnExit idle{h, s};
   note_learned(h, num_frames, learn);
   if (h->lkernel) {
     htmsp::LocalArgs a;
@@ -981,7 +1091,7 @@ int sp_step_local(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames,
                                               dim3(htmsp::kPersistWaves * 64), args, 0, s);
     if (e != hipSuccess) return hip_fail(e, "persistent local step launch");
     h->xloc_frames += num_frames;
-    return ok();
+    return add_histogram_active(h, active_dev, num_frames, s);
   }
   for (uint32_t t = 0; t < num_frames; ++t) {
     const uint32_t* frame = frames_dev + (size_t)t * sh.W;
@@ -993,7 +1103,7 @@ int sp_step_local(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames,
     if (e == hipSuccess && learn) e = htmsp::launch_learn_active(h->idx, h->perm, frame, act, sh, s);
     if (e != hipSuccess) return hip_fail(e, "local step launch");
   }
-  return ok();
+  return add_histogram_active(h, active_dev, num_frames, s);
 }
 
 }  // extern "C"
@@ -1042,6 +1152,7 @@ int sp_step_boost(sp_handle* h, const sp_boost_config* bc, const uint32_t* frame
   if (num_frames == 0) return ok();
   DeviceScope ds(h->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
+  IdleOnExit idle{h, s};
   rc = ensure_boost(h, s);
   if (rc) return rc;
   const Shape& sh = h->sh;
@@ -1102,6 +1213,7 @@ int sp_boost_state(sp_handle* h, uint32_t* active_duty_dev, uint32_t* overlap_du
   if (rc) return rc;
   DeviceScope ds(h->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
+  IdleOnExit idle{h, s};
   rc = ensure_boost(h, s);
   if (rc) return rc;
   const size_t n = sizeof(uint32_t) * h->sh.C;
@@ -1122,6 +1234,7 @@ int sp_boost_reset(sp_handle* h, void* stream) {
   if (rc) return rc;
   if (!h->boost_mem) return ok();
   DeviceScope ds(h->device);
+  IdleOnExit idle{h, static_cast<hipStream_t>(stream)};
   hipError_t e = htmsp::launch_boost_init(h->boost_mem, h->boost_mem + h->sh.C,
                                           h->boost_mem + 2 * (size_t)h->sh.C, h->sh.C,
                                           static_cast<hipStream_t>(stream));
@@ -1211,13 +1324,18 @@ int sp_destroy(sp_handle* h) {
   int rc = SP_OK;
   {
     DeviceScope ds(h->device);
-    hipError_t e = hipDeviceSynchronize();
-    if (e == hipSuccess) e = hipFree(h->ws);
+    // the handle's own work, not the whole device
+    hipError_t e = h->idle_used ? hipEventSynchronize(h->idle) : hipSuccess;
+    if (e == hipSuccess) e = many_wait(h);
+    // buffers of batched inference and boosting (hipFree waits for the device)
     if (e == hipSuccess && h->infer_list) e = hipFree(h->infer_list);
     if (e == hipSuccess && h->infer_ov) e = hipFree(h->infer_ov);
     if (e == hipSuccess && h->boost_mem) e = hipFree(h->boost_mem);
     if (e == hipSuccess && h->mfma_mask) e = hipFree(h->mfma_mask);
     if (e == hipSuccess && h->mfma_part) e = hipFree(h->mfma_part);
+    if (e == hipSuccess && !ws_give(h->device, h->ws, h->ws_bytes)) e = hipFree(h->ws);
+    const hipError_t e2 = hipEventDestroy(h->idle);
+    if (e == hipSuccess) e = e2;
     if (e != hipSuccess) rc = hip_fail(e, "destroy");
   }
   delete h;

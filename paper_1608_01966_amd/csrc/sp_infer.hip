@@ -8,6 +8,8 @@
 // stages one whole frame at a time in LDS (a 960x540 frame is 64 800 B), and
 // counts the connected inputs that are on with one LDS read each; the
 // workgroups that share a frame run on one XCD so its L2 serves them all.
+// Columns with more connected synapses than the registers hold read their
+// lists from device memory instead (k_infer_gather_long).
 // A second kernel resolves the global top-k of every frame, one wave per
 // frame, on overlaps packed four per 64-bit word.
 #include <type_traits>
@@ -116,6 +118,43 @@ __global__ __launch_bounds__(kInferThreads) void k_infer_gather(
           acc += __builtin_amdgcn_ubfe(word, e, 1);
         }
       }
+    }
+    if (col_ok) ov_out[(size_t)f * sh.C + c] = acc >= sh.m ? (int32_t)acc : 0;
+  }
+}
+
+// Gather overlaps for lists longer than the register-resident kernels hold:
+// the same block mapping and frame staging as k_infer_gather, but each
+// thread reads its column's list entries from device memory for every frame
+// (slot-major, so a wave's reads of one slot are coalesced; the lists stay
+// in L2 across the frames of a group).
+template <bool LDS>
+__global__ __launch_bounds__(kInferThreads) void k_infer_gather_long(
+    const uint32_t* __restrict__ frames, uint32_t F, const uint32_t* __restrict__ list,
+    const uint32_t* __restrict__ cnt, Shape sh, uint32_t frames_per_group, uint32_t col_blocks,
+    uint32_t groups, int32_t* __restrict__ ov_out) {
+  extern __shared__ uint32_t fr[];
+  const uint32_t per = 8 * col_blocks;
+  const uint32_t fg = (blockIdx.x / per) * 8 + blockIdx.x % 8;
+  const uint32_t cb = (blockIdx.x % per) / 8;
+  if (fg >= groups) return;  // whole workgroup
+  const uint32_t c = cb * kInferThreads + threadIdx.x;
+  const bool col_ok = c < sh.C;
+  const uint32_t n = col_ok ? cnt[c] : 0u;
+  const uint32_t f0 = fg * frames_per_group;
+  const uint32_t f1 = min(F, f0 + frames_per_group);
+  for (uint32_t f = f0; f < f1; ++f) {
+    const uint32_t* frame = frames + (size_t)f * sh.W;
+    if constexpr (LDS) {
+      __syncthreads();
+      for (uint32_t i = threadIdx.x; i < sh.W; i += kInferThreads) fr[i] = frame[i];
+      __syncthreads();
+    }
+    uint32_t acc = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+      const uint32_t e = list[(size_t)i * sh.C + c];
+      const uint32_t word = LDS ? entry_load(fr, e) : frame[entry_word(e)];
+      acc += __builtin_amdgcn_ubfe(word, e, 1);
     }
     if (col_ok) ov_out[(size_t)f * sh.C + c] = acc >= sh.m ? (int32_t)acc : 0;
   }
@@ -303,6 +342,23 @@ hipError_t launch_gather_db_t(const uint32_t* frames, uint32_t F, const uint32_t
   return hipGetLastError();
 }
 
+template <bool LDS>
+hipError_t launch_gather_long_t(const uint32_t* frames, uint32_t F, const uint32_t* list,
+                                const uint32_t* cnt, const Shape& sh, int32_t* ov, uint32_t cus,
+                                hipStream_t s) {
+  const uint32_t col_blocks = (sh.C + kInferThreads - 1) / kInferThreads;
+  // about four blocks per CU, frame groups a multiple of 8
+  uint32_t groups = (4 * cus + col_blocks - 1) / col_blocks;
+  groups = max(1u, min(groups, F));
+  const uint32_t fpg = (F + groups - 1) / groups;
+  groups = (F + fpg - 1) / fpg;
+  const uint32_t padded = (groups + 7) / 8 * 8;
+  const size_t lds = LDS ? sizeof(uint32_t) * (size_t)sh.W : 0;
+  hipLaunchKernelGGL((k_infer_gather_long<LDS>), dim3(padded * col_blocks), dim3(kInferThreads),
+                     lds, s, frames, F, list, cnt, sh, fpg, col_blocks, groups, ov);
+  return hipGetLastError();
+}
+
 hipError_t launch_gather_db(uint32_t maxn, const uint32_t* frames, uint32_t F,
                             const uint32_t* list, const uint32_t* cnt, const Shape& sh,
                             int32_t* ov, uint32_t cus, hipStream_t s) {
@@ -339,6 +395,13 @@ hipError_t launch_infer_gather(uint32_t maxn, const uint32_t* frames, uint32_t F
   if (e == hipSuccess)
     e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
   if (e != hipSuccess) return e;
+  if (maxn > infer_max_list()) {
+    // every entry is a real connected input (no padding read), so the frame
+    // needs no zero word
+    const bool lds = sizeof(uint32_t) * (size_t)sh.W <= infer_lds_limit();
+    return lds ? launch_gather_long_t<true>(frames, F, list, cnt, sh, ov, cus, s)
+               : launch_gather_long_t<false>(frames, F, list, cnt, sh, ov, cus, s);
+  }
   // two buffers, each the frame plus the zero word
   if (sh.W + 1 <= kDbBufWords && sizeof(uint32_t) * 2 * kDbBufWords <= (size_t)lds_max)
     return launch_gather_db(maxn, frames, F, list, cnt, sh, ov, cus, s);

@@ -207,6 +207,9 @@ hipError_t launch_learn_active(const uint32_t* idx, float* perm, const uint32_t*
                                const uint8_t* active, const Shape& sh, hipStream_t s);
 
 // Adds 1 to hist[c] for every entry c >= 0 of winners[n] (sp_hist.hip).
+// Adds, for every column c, the frames of active [F][C] (0/1) with c active.
+hipError_t launch_hist_add_active(const uint8_t* active, uint32_t F, uint32_t C, uint32_t* hist,
+                                  hipStream_t s);
 hipError_t launch_hist_add(const int32_t* winners, size_t n, uint32_t C, uint32_t* hist,
                            hipStream_t s);
 

@@ -94,3 +94,37 @@ def test_boosted_step(C):
     assert np.array_equal(win.cpu().numpy(), e_win)
     assert np.array_equal(h.cpu().numpy().astype(np.uint32), oracle.histogram(e_win, C))
     pool.close()
+
+
+@pytest.mark.parametrize("persistent", [True, False])
+def test_local_step(persistent):
+    """sp_step_local adds each frame's active columns (its output is an
+    active mask, not a winner list) on the persistent and the per-frame
+    executions; two calls accumulate."""
+    import torch
+    if persistent:
+        w = synth.workload_paper_scale(frames=24, columns=1024, synapses=128)
+        w.cfg["winners"] = 4
+        grid_w, radius = 32, 3
+    else:
+        # more columns than one persistent launch exchanges: per-frame launches
+        cfg = synth.sp_config(20_000, 5000, 16, 2, 3)
+        w = synth.random_instance(7, cfg, 12, density=0.1)
+        grid_w, radius = 100, 2
+    cfg = w.cfg
+    C, F = cfg["num_columns"], w.frames.shape[0]
+    _, e_act, _ = oracle.run_local(cfg, w.idx, w.perm, w.frames, grid_w, radius, cfg["winners"])
+    pool = sp.SpatialPooler(cfg, w.idx, w.perm)
+    assert (pool.local_kernel == "k_sp_persistent_local") == persistent
+    h = _hist(C)
+    pool.set_histogram(h)
+    frames = torch.from_numpy(np.ascontiguousarray(w.frames).view(np.int32)).cuda()
+    act = torch.empty((F, C), dtype=torch.uint8, device="cuda")
+    half = F // 2
+    sp.sp_step_local(pool.handle, cfg, frames[:half], True, grid_w, radius, None, act[:half])
+    sp.sp_step_local(pool.handle, cfg, frames[half:], True, grid_w, radius, None, act[half:])
+    pool.sync()
+    want = e_act.astype(np.int64).sum(axis=0)
+    assert want.sum() > 0
+    assert np.array_equal(h.cpu().numpy().astype(np.int64), want)
+    pool.close()

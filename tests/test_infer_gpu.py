@@ -127,14 +127,22 @@ def test_lists_rebuilt_after_learning(mode):
     pool.close()
 
 
-def test_lists_longer_than_registers_rejected():
-    cfg = synth.sp_config(5000, 16, 300, 1, 4, connected_q8=0)
-    w = synth.random_instance(24, cfg, frames=2)
-    pool = sp.SpatialPooler(cfg, w.idx, w.perm)
-    with pytest.raises(sp.SpError, match="connected synapses") as e:
-        pool.infer(w.frames)
-    assert e.value.code == sp.SP_EINVAL
-    pool.close()
+@pytest.mark.parametrize("case", ["all_connected_300", "s512_960x540", "4096_global_frame"])
+def test_gather_lists_longer_than_registers(case):
+    """Columns with more than 256 connected synapses: the gather mode reads
+    their lists from device memory (frames staged in LDS, or read from device
+    memory when a frame is larger than LDS) with the same results."""
+    if case == "all_connected_300":
+        cfg = synth.sp_config(5000, 16, 300, 1, 4, connected_q8=0)
+        w = synth.random_instance(24, cfg, frames=5, density=0.2)
+    elif case == "s512_960x540":
+        # the batched-training and serving poolers go up to 512 synapses
+        cfg = synth.sp_config(960 * 540, 640, 512, 4, 25)
+        w = synth.random_instance(25, cfg, frames=9, density=0.05, shape=(960, 540), blobs=True)
+    else:
+        cfg = synth.sp_config(1 << 21, 300, 4096, 2, 12, connected_q8=0)
+        w = synth.random_instance(28, cfg, frames=3, density=0.02)
+    check_infer(w, mode=sp.SP_INFER_GATHER)
 
 
 def test_matrix_product_any_connected_count():

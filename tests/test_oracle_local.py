@@ -108,7 +108,8 @@ def test_planted_mistakes_are_caught(name, tmp_path, monkeypatch):
     c.write_text(src.replace(before, after, 1))
     so = tmp_path / "libmut.so"
     subprocess.check_call(["gcc", "-O1", "-std=c99", "-fPIC", "-shared", "-I", here, str(c),
-                           os.path.join(here, "enc_oracle.c"), "-o", str(so)])
+                           os.path.join(here, "sp_oracle_mt.c"),
+                           os.path.join(here, "enc_oracle.c"), "-pthread", "-o", str(so)])
     monkeypatch.setattr(oracle, "_LIB_PATH", str(so))
     monkeypatch.setattr(oracle, "_lib", None)
     caught = 0

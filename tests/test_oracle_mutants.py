@@ -67,10 +67,13 @@ def swap_lib(monkeypatch, tmp_path):
         c = tmp_path / "mutant.c"
         c.write_text(src_text)
         so = tmp_path / f"mutant_{abs(hash(src_text))}.so"
-        # the library also carries the (unmutated) encoder oracle
+        # the library also carries the threaded runner and the (unmutated)
+        # encoder oracle
         subprocess.check_call(["gcc", "-O1", "-std=c99", "-fPIC", "-shared", "-I",
                                os.path.dirname(SRC), str(c),
-                               os.path.join(os.path.dirname(SRC), "enc_oracle.c"), "-o", str(so)])
+                               os.path.join(os.path.dirname(SRC), "sp_oracle_mt.c"),
+                               os.path.join(os.path.dirname(SRC), "enc_oracle.c"), "-pthread",
+                               "-o", str(so)])
         monkeypatch.setattr(oracle, "_LIB_PATH", str(so))
         monkeypatch.setattr(oracle, "_lib", None)
     yield use

@@ -68,22 +68,84 @@ def measured_traffic(profile: str, kernel: str, kernel_ms: float):
     return b / (kernel_ms * 1e-3) / 1e9, b
 
 
-def cpu_baseline(w, learn: bool, budget_s: float, what: str) -> dict:
-    """The oracle, single-threaded, on the first frames of the same workload
-    (as many as fit the time budget, doubling from 25)."""
-    import oracle
-    F = w.frames.shape[0]
+def host_cores() -> int:
+    return len(os.sched_getaffinity(0))
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _sample(fn, F: int, budget_s: float):
+    """Frames (doubling from 25, at most F) that fn(n) takes at least
+    budget_s / 3 on; returns (n, seconds)."""
     n = min(25, F)
     while True:
         t0 = time.perf_counter()
-        oracle.run(w.cfg, w.idx, w.perm, w.frames[:n], learn=learn, want_overlaps=False)
+        fn(n)
         dt = time.perf_counter() - t0
         if dt > budget_s / 3 or n >= F:
-            break
+            return n, dt
         n = min(2 * n, F)
-    return {"value": n / dt, "unit": "frames/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {n} frames of the same {what} from the same state, "
-                      f"{dt:.2f} s single-threaded"}
+
+
+def cpu_baseline(w, learn: bool, budget_s: float, what: str) -> dict:
+    """The oracle on the first frames of the same workload (as many as fit
+    the time budget): on every host core the process may use (columns split
+    over threads, the inhibition on one), and single-threaded."""
+    import oracle
+    F = w.frames.shape[0]
+    cores = host_cores()
+    n1, dt1 = _sample(lambda n: oracle.run(w.cfg, w.idx, w.perm, w.frames[:n], learn=learn,
+                                           want_overlaps=False), F, budget_s)
+    nm, dtm = _sample(lambda n: oracle.run_threads(w.cfg, w.idx, w.perm, w.frames[:n], cores,
+                                                   learn=learn, want_overlaps=False),
+                      F, budget_s)
+    return {"value": nm / dtm, "unit": "frames/s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "sample": f"first {nm} frames of the same {what} from the same state, "
+                      f"{dtm:.2f} s on {cores} threads (columns split per frame, "
+                      f"inhibition on one thread)",
+            "single_thread": {"value": n1 / dt1, "unit": "frames/s", "cores": 1,
+                              "sample": f"first {n1} frames, {dt1:.2f} s"}}
+
+
+def copy_peak(torch, mib: int = 1024, reps: int = 5) -> float:
+    """Device-to-device copy rate (GB/s, bytes read plus bytes written) of a
+    `mib` MiB buffer, best of `reps`: the HBM bandwidth a plain streaming
+    kernel reaches on this device, measured in the same run."""
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = float("inf")
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del src, dst
+    return 2 * n * 4 / (best * 1e-3) / 1e9
+
+
+def with_measured_peak(roof: dict, peak_gbs: float) -> dict:
+    """Adds the copy rate measured in this run beside the published peak."""
+    if roof is not None and roof.get("unit") == "GB/s":
+        roof["measured_copy_peak"] = peak_gbs
+        roof["frac_of_measured_peak"] = roof["achieved"] / peak_gbs
+    elif roof is not None:
+        roof["measured_copy_peak_gbs"] = peak_gbs
+    return roof
 
 
 def timed(run, steps: int):
@@ -166,6 +228,68 @@ def bench_learn(args, torch, sp, synth):
         plain = pf / (time.perf_counter() - tp0)
         ppool.close()
 
+    # End to end: the frames start in pinned host memory and are uploaded
+    # on the same stream before the step (the paper's timing with transfers).
+    host = torch.from_numpy(np.ascontiguousarray(w.frames).view(np.int32)).pin_memory()
+    dev2 = torch.empty_like(frames)
+
+    def run_e2e(ev0=None, ev1=None):
+        pool.perm.copy_(perm0)
+        if ev0 is not None:
+            ev0.record(stream)
+        dev2.copy_(host, non_blocking=True)
+        sp.sp_step(pool.handle, cfg, dev2, True, ov, win, stream)
+        if ev1 is not None:
+            ev1.record(stream)
+
+    run_e2e()
+    pool.sync()
+    e2e_wall, e2e_ms = timed(run_e2e, max(1, args.steps // 2))
+    pool.sync()
+    e2e = {"frames_per_s": max(1, args.steps // 2) * F / e2e_wall, "ms_per_step": e2e_ms,
+           "upload_bytes_per_step": int(host.numel() * 4),
+           "what": "pinned host frames uploaded on the step's stream, then the step"}
+
+    sweep = []
+    if args.sweep:
+        for sc in (256, 512, 1024, 2048):
+            for ss in (32, 64, 128, 256):
+                if (sc, ss) == (C, S):
+                    continue
+                ws = synth.workload_paper_scale(frames=args.sweep_frames, columns=sc,
+                                                synapses=ss)
+                sfr = torch.from_numpy(np.ascontiguousarray(ws.frames).view(np.int32)).cuda()
+                sp2 = sp.SpatialPooler(ws.cfg, ws.idx, ws.perm)
+                sp0 = sp2.perm.clone()
+                sov = torch.empty((args.sweep_frames, sc), dtype=torch.int32, device="cuda")
+                swin = torch.empty((args.sweep_frames, ws.cfg["winners"]), dtype=torch.int32,
+                                   device="cuda")
+
+                def srun(ev0=None, ev1=None, sp2=sp2, sp0=sp0, ws=ws, sfr=sfr, sov=sov,
+                         swin=swin):
+                    sp2.perm.copy_(sp0)
+                    if ev0 is not None:
+                        ev0.record(stream)
+                    sp.sp_step(sp2.handle, ws.cfg, sfr, True, sov, swin, stream)
+                    if ev1 is not None:
+                        ev1.record(stream)
+
+                srun()
+                sp2.sync()
+                swall, sms = timed(srun, 3)
+                sp2.sync()
+                sab = algorithmic_bytes_learn(ws.cfg, swin.cpu().numpy())
+                sweep.append({"columns": sc, "synapses": ss, "frames": args.sweep_frames,
+                              "frames_per_s": 3 * args.sweep_frames / swall,
+                              "synapse_updates_per_s": 3 * args.sweep_frames * sc * ss / swall,
+                              "kernel_ms_per_launch": sms, "path": sp2.kernel,
+                              "roofline_frac": sab / (sms * 1e-3) / 1e9 / HBM_PEAK_GBS})
+                sp2.close()
+        sweep.append({"columns": C, "synapses": S, "frames": F, "frames_per_s": fps,
+                      "synapse_updates_per_s": fps * C * S, "kernel_ms_per_launch": kernel_ms,
+                      "path": kname, "roofline_frac": achieved / HBM_PEAK_GBS})
+        sweep.sort(key=lambda r: (r["columns"], r["synapses"]))
+
     cpu = None if args.no_cpu_baseline else cpu_baseline(
         w, True, args.cpu_budget, f"{F}-frame learning workload")
     line = {
@@ -187,6 +311,8 @@ def bench_learn(args, torch, sp, synth):
                      "algorithmic_bytes_per_launch": abytes,
                      "counter_bytes_per_launch": traffic_bytes},
         "plain_one_frame_per_launch_frames_per_s": plain,
+        "end_to_end_pinned_upload": e2e,
+        "sweep": sweep,
         "cpu_baseline": cpu,
     }
     pool.close()
@@ -261,6 +387,26 @@ def bench_infer(args, torch, sp, synth):
             fn(pool.handle, cfg, frames[:pf], False, pov, pwin, stream)
             pool.sync()
             comp[name + "_frames_per_s"] = pf / (time.perf_counter() - t0)
+
+    # end to end: the frames uploaded from pinned host memory before the call
+    host = torch.from_numpy(np.ascontiguousarray(w.frames).view(np.int32)).pin_memory()
+    dev2 = torch.empty_like(frames)
+
+    def run_e2e(ev0=None, ev1=None):
+        if ev0 is not None:
+            ev0.record(stream)
+        dev2.copy_(host, non_blocking=True)
+        sp.sp_infer(pool.handle, cfg, dev2, mode, ov, win, stream)
+        if ev1 is not None:
+            ev1.record(stream)
+
+    run_e2e()
+    pool.sync()
+    e2e_wall, e2e_ms = timed(run_e2e, max(1, args.steps // 2))
+    comp["end_to_end_pinned_upload"] = {
+        "frames_per_s": max(1, args.steps // 2) * F / e2e_wall, "ms_per_step": e2e_ms,
+        "upload_bytes_per_step": int(host.numel() * 4),
+        "what": "pinned host frames uploaded on the call's stream, then the call"}
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(
         w, False, args.cpu_budget, f"{F}-frame inference batch")
@@ -344,19 +490,33 @@ def bench_multi(args, torch, sp, synth):
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        n, dt = 2, 0.0
-        while True:
-            t0 = time.perf_counter()
-            for w in ws:
-                oracle.run(w.cfg, w.idx, w.perm, w.frames[:n], learn=True, want_overlaps=False)
-            dt = time.perf_counter() - t0
-            if dt > args.cpu_budget / 3 or n >= args.multi_frames:
-                break
-            n = min(2 * n, args.multi_frames)
-        cpu = {"value": n * len(ws) / dt, "unit": "instance-frames/s", "cores": 1,
-               "kind": "oracle", "sample": f"first {n} frames of each of the {len(ws)} "
-                                           f"instances from the same states, {dt:.2f} s "
-                                           f"single-threaded"}
+        cores = host_cores()
+
+        def sample(threads):
+            n, dt = 2, 0.0
+            while True:
+                t0 = time.perf_counter()
+                for w in ws:
+                    if threads == 1:
+                        oracle.run(w.cfg, w.idx, w.perm, w.frames[:n], learn=True,
+                                   want_overlaps=False)
+                    else:
+                        oracle.run_threads(w.cfg, w.idx, w.perm, w.frames[:n], threads,
+                                           learn=True, want_overlaps=False)
+                dt = time.perf_counter() - t0
+                if dt > args.cpu_budget / 3 or n >= args.multi_frames:
+                    return n, dt
+                n = min(2 * n, args.multi_frames)
+
+        n1, dt1 = sample(1)
+        nm, dtm = sample(cores)
+        cpu = {"value": nm * len(ws) / dtm, "unit": "instance-frames/s", "cores": cores,
+               "kind": "oracle", "cpu_model": cpu_model(),
+               "sample": f"first {nm} frames of each of the {len(ws)} instances from the same "
+                         f"states, {dtm:.2f} s on {cores} threads (each instance's columns "
+                         f"split per frame)",
+               "single_thread": {"value": n1 * len(ws) / dt1, "unit": "instance-frames/s",
+                                 "cores": 1, "sample": f"first {n1} frames, {dt1:.2f} s"}}
     line = {
         "metric": "SP instance-frames/s, 64 uneven instances, learning on",
         "value": ips, "unit": "instance-frames/s", "n_gpus": 1, "steps": args.steps,
@@ -712,6 +872,9 @@ def main() -> int:
     ap.add_argument("--plain-frames", type=int, default=200,
                     help="frames timed through the one-frame-per-launch path (0: skip)")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
+    ap.add_argument("--no-sweep", dest="sweep", action="store_false",
+                    help="skip the column x synapse sweep of --workload learn")
+    ap.add_argument("--sweep-frames", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibration-copy-mb", type=int, default=0,
                     help="before timing, run one elementwise int32 copy of this many MiB "
@@ -739,7 +902,9 @@ def main() -> int:
     fn = {"learn": bench_learn, "infer": bench_infer, "multi": bench_multi,
           "serve": bench_serve, "encode": bench_encode, "local": bench_local,
           "boost": bench_boost}[args.workload]
+    peak = copy_peak(torch)
     line = fn(args, torch, sp, synth)
+    with_measured_peak(line.get("roofline"), peak)
     print(json.dumps(line), flush=True)
     return 0
 

@@ -36,9 +36,11 @@
  * borrows for its lifetime; the library reads idx and reads/writes perm in
  * place.  frames, overlaps and winners are caller-owned per call.  The
  * library allocates a small per-handle workspace (sp_workspace_bytes) in
- * sp_create and, on the first sp_infer, the compacted connected lists
+ * sp_create (or reuses one a destroyed handle left in the library's pool)
+ * and, on the first sp_infer, the compacted connected lists
  * (4 * (S * C + C) bytes) plus, when sp_infer gets no overlap buffer, an
- * [F][C] scratch; sp_destroy frees all of it.
+ * [F][C] scratch, and on the first sp_step_boost the boost state
+ * (13 C bytes, rounded up); sp_destroy frees or pools all of it.
  *
  * Streams: `stream` is a hipStream_t (NULL = the null stream).  Steps are
  * enqueued and return at once; results are valid once the stream has
@@ -381,8 +383,13 @@ int sp_test_stall(sp_handle* h, uint32_t spin_limit);
  * step on this handle (SP_EDEVICE, after which the handle is SP_EBROKEN). */
 int sp_sync(sp_handle* h, void* stream);
 
-/* Frees the workspace (synchronising the device first).  NULL is accepted.
- * The borrowed state is left as it is. */
+/* Waits for the work enqueued on this handle (its own calls, not the rest
+ * of the device), returns its workspace to a per-device pool that later
+ * sp_create calls reuse (at most 256 MiB per device, held until the process
+ * ends, so that retiring a handle never waits for other streams), and frees
+ * the buffers of batched inference and boosting if it has any (that free
+ * waits for the device).  NULL is accepted.  The borrowed state is left as
+ * it is; the caller may free it once this returns. */
 int sp_destroy(sp_handle* h);
 
 /* Message for the calling thread's last failure ("" if none).  Valid until

@@ -99,6 +99,13 @@ def _load():
         lib.spo_run_local.argtypes = [ctypes.POINTER(_Cfg), P, P, P, ctypes.c_uint32, ctypes.c_int,
                                       ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, P, P]
         lib.spo_run_local.restype = ctypes.c_int
+        lib.spo_adapt_radius.argtypes = [ctypes.POINTER(_Cfg), P, P, ctypes.c_uint32,
+                                         ctypes.c_uint32, ctypes.c_uint32]
+        lib.spo_adapt_radius.restype = ctypes.c_uint32
+        lib.spo_run_local_adaptive.argtypes = [ctypes.POINTER(_Cfg), P, P, P, ctypes.c_uint32,
+                                               ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32,
+                                               ctypes.c_uint32, ctypes.c_uint32, P, P, P]
+        lib.spo_run_local_adaptive.restype = ctypes.c_uint32
         lib.enc_reduce.argtypes = [P, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, P]
         lib.enc_reduce.restype = None
         lib.enc_gray.argtypes = [P, ctypes.c_uint32, P]
@@ -288,6 +295,38 @@ def run_local(cfg: dict, idx: np.ndarray, perm: np.ndarray, frames: np.ndarray, 
 
 
 # ---- adaptive video encoder (Section 3.1.2), readings E1-E6 in enc_oracle.h
+
+def adapt_radius(cfg: dict, idx: np.ndarray, perm: np.ndarray, in_w: int, grid_w: int,
+                 radius: int) -> int:
+    """The radius after a learning frame from the state it left (reading L5)."""
+    idx = np.ascontiguousarray(idx, dtype=np.uint32)
+    perm = np.ascontiguousarray(perm, dtype=np.float64)
+    c = _cfg(cfg)
+    return int(_load().spo_adapt_radius(ctypes.byref(c), _ptr(idx), _ptr(perm), int(in_w),
+                                        int(grid_w), int(radius)))
+
+
+def run_local_adaptive(cfg: dict, idx: np.ndarray, perm: np.ndarray, frames: np.ndarray,
+                       in_w: int, grid_w: int, radius: int, n: int, learn: bool = True):
+    """Local inhibition with the radius adapted after every learning frame.
+    Returns (overlaps int32 [F][C], active uint8 [F][C], perm float64,
+    radii uint32 [F] (each frame's radius), final radius)."""
+    idx = np.ascontiguousarray(idx, dtype=np.uint32)
+    perm = np.array(perm, dtype=np.float64, order="C", copy=True)
+    frames = np.ascontiguousarray(frames, dtype=np.uint32)
+    F = frames.shape[0]
+    C = int(cfg["num_columns"])
+    ov = np.zeros((F, C), dtype=np.int32)
+    act = np.zeros((F, C), dtype=np.uint8)
+    radii = np.zeros(F, dtype=np.uint32)
+    c = _cfg(cfg)
+    r = _load().spo_run_local_adaptive(ctypes.byref(c), _ptr(idx), _ptr(perm), _ptr(frames), F,
+                                       int(bool(learn)), int(in_w), int(grid_w), int(radius),
+                                       int(n), _ptr(ov), _ptr(act), _ptr(radii))
+    if r == 0:
+        raise ValueError("oracle rejected its arguments")
+    return ov, act, perm, radii, int(r)
+
 
 def enc_reduce(rgb: np.ndarray, factor: int) -> np.ndarray:
     """uint8 [H][W][3] -> uint8 [H/f][W/f][3], block means rounded half up."""

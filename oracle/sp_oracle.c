@@ -191,6 +191,67 @@ int spo_run_local(const spo_config* cfg, const uint32_t* idx, double* perm,
   return 0;
 }
 
+uint32_t spo_adapt_radius(const spo_config* cfg, const uint32_t* idx, const double* perm,
+                          uint32_t in_w, uint32_t grid_w, uint32_t radius) {
+  const uint32_t C = cfg->num_columns, S = cfg->synapses_per_column, N = cfg->input_bits;
+  const uint64_t in_h = ((uint64_t)N + in_w - 1) / in_w;
+  const uint64_t grid_h = ((uint64_t)C + grid_w - 1) / grid_w;
+  uint64_t A = 0, n = 0;
+  for (uint32_t c = 0; c < C; ++c) {
+    uint32_t x0 = 0, x1 = 0, y0 = 0, y1 = 0;
+    int any = 0;
+    for (uint32_t s = 0; s < S; ++s) {
+      const size_t syn = (size_t)c * S + s;
+      if (!synapse_connected(cfg, perm[syn])) continue;
+      const uint32_t x = idx[syn] % in_w, y = idx[syn] / in_w;
+      if (!any || x < x0) x0 = x;
+      if (!any || x > x1) x1 = x;
+      if (!any || y < y0) y0 = y;
+      if (!any || y > y1) y1 = y;
+      any = 1;
+    }
+    if (!any) continue;
+    A += (uint64_t)(x1 - x0 + 1) + (uint64_t)(y1 - y0 + 1);
+    n += 1;
+  }
+  if (n == 0) return radius;
+  const unsigned __int128 num =
+      (unsigned __int128)A * ((uint64_t)grid_w * in_h + grid_h * (uint64_t)in_w);
+  const unsigned __int128 den = (unsigned __int128)8 * n * in_w * in_h;
+  const uint64_t r = (uint64_t)(num / den);
+  return r < 1 ? 1u : (r > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)r);
+}
+
+uint32_t spo_run_local_adaptive(const spo_config* cfg, const uint32_t* idx, double* perm,
+                                const uint32_t* frames, uint32_t num_frames, int learn,
+                                uint32_t in_w, uint32_t grid_w, uint32_t radius, uint32_t n,
+                                int32_t* overlaps, uint8_t* active, uint32_t* radii) {
+  if (!cfg || !idx || !perm || (!frames && num_frames) || (!active && num_frames)) return 0;
+  const uint32_t C = cfg->num_columns;
+  if (C == 0 || cfg->synapses_per_column == 0 || cfg->input_bits == 0 || grid_w == 0 ||
+      grid_w > C || in_w == 0 || in_w > cfg->input_bits || n == 0 || radius == 0)
+    return 0;
+  const size_t W = ((size_t)cfg->input_bits + 31) / 32;
+  for (size_t i = 0; i < (size_t)C * cfg->synapses_per_column; ++i)
+    if (idx[i] >= cfg->input_bits) return 0;
+  int32_t* ov = (int32_t*)malloc(sizeof(int32_t) * C);
+  if (!ov) return 0;
+  for (uint32_t t = 0; t < num_frames; ++t) {
+    const uint32_t* frame = frames + (size_t)t * W;
+    uint8_t* act = active + (size_t)t * C;
+    if (radii) radii[t] = radius;
+    spo_overlap(cfg, idx, perm, frame, ov);
+    spo_inhibit_local(ov, C, grid_w, radius, n, act);
+    if (learn) {
+      spo_learn(cfg, idx, perm, frame, act);
+      radius = spo_adapt_radius(cfg, idx, perm, in_w, grid_w, radius);
+    }
+    if (overlaps) memcpy(overlaps + (size_t)t * C, ov, sizeof(int32_t) * C);
+  }
+  free(ov);
+  return radius;
+}
+
 int spo_run_boost(const spo_config* cfg, const spo_boost* bc, const uint32_t* idx, double* perm,
                   const uint32_t* frames, uint32_t num_frames, int learn, uint32_t* adc,
                   uint32_t* odc, uint32_t* boost, int32_t* overlaps, int32_t* winners) {

@@ -95,6 +95,34 @@ int spo_run_local(const spo_config* cfg, const uint32_t* idx, double* perm,
                   const uint32_t* frames, uint32_t num_frames, int learn, uint32_t grid_w,
                   uint32_t radius, uint32_t n, int32_t* overlaps, uint8_t* active);
 
+/* Inhibition radius adaptation (Section 4.4: a change of winners_set_size
+ * is compensated by adapting the inhibition radius, which the paper takes
+ * from the whitepaper; its rule sets the radius, after each learning frame,
+ * to the average connected receptive field size of the columns).  Reading
+ * L5: the input is an image of in_w pixels per row (pixel p at x = p mod
+ * in_w, y = p div in_w, in_h = ceil(N / in_w) rows) and the columns a grid
+ * of grid_w per row (grid_h = ceil(C / grid_w) rows).  A column with at
+ * least one connected synapse has the extent span_x = max x - min x + 1 and
+ * span_y = max y - min y + 1 of its connected inputs; over the n such
+ * columns the mean extent is A / (2 n), A = sum of span_x + span_y; it is
+ * carried to the column grid by the mean of the two grid-per-input ratios,
+ * (grid_w / in_w + grid_h / in_h) / 2, giving a diameter d, and the radius
+ * is (d - 1) / 2 rounded half up, at least 1:
+ *   radius = max(1, floor(A (grid_w in_h + grid_h in_w) / (8 n in_w in_h))).
+ * With no connected synapse anywhere (n = 0) the radius stays as it was.
+ * Returns the new radius. */
+uint32_t spo_adapt_radius(const spo_config* cfg, const uint32_t* idx, const double* perm,
+                          uint32_t in_w, uint32_t grid_w, uint32_t radius);
+
+/* spo_run_local with the radius adapted after every learning frame: frame t
+ * uses the radius left by frame t - 1 (the first frame uses `radius`);
+ * radii [F] (may be NULL) receives the radius each frame used.  Returns the
+ * radius after the last frame, or 0 on a bad argument. */
+uint32_t spo_run_local_adaptive(const spo_config* cfg, const uint32_t* idx, double* perm,
+                                const uint32_t* frames, uint32_t num_frames, int learn,
+                                uint32_t in_w, uint32_t grid_w, uint32_t radius, uint32_t n,
+                                int32_t* overlaps, uint8_t* active, uint32_t* radii);
+
 /* Boosting and duty cycles (Algorithm 1 multiplies each gated overlap by the
  * column's boost, which Section 3.2.2 computes in the kernel; the update
  * rules are the whitepaper's, spatial pooler phase 3), in exact fixed

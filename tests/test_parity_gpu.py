@@ -103,9 +103,13 @@ def test_paper_scale_plain_200_frames():
     check(synth.workload_paper_scale(frames=200), plain=True)
 
 
-@pytest.mark.parametrize("C,S", [(256, 32), (512, 64), (2048, 128), (2048, 256), (256, 256)])
+SWEEP = [(c, s) for c in (256, 512, 1024, 2048) for s in (32, 64, 128, 256)]
+
+
+@pytest.mark.parametrize("C,S", SWEEP, ids=[f"C{c}_S{s}" for c, s in SWEEP])
 def test_paper_scale_sweep_points(C, S):
-    check(synth.workload_paper_scale(frames=40, columns=C, synapses=S), expect_persistent=True)
+    """Every point of the column x synapse sweep the benchmark times, at 960x540."""
+    check(synth.workload_paper_scale(frames=41, columns=C, synapses=S), expect_persistent=True)
 
 
 # One shape per instance of the one-column-group-per-wave persistent kernel

@@ -303,6 +303,29 @@ int sp_step_local(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames,
                   uint32_t grid_w, uint32_t radius, int32_t* overlaps_dev, uint8_t* active_dev,
                   void* stream);
 
+/* sp_step_local with the inhibition radius adapted after every learning
+ * frame (Section 4.4: a change of winners_set_size is compensated by
+ * adapting the inhibition radius, which the paper takes from the
+ * whitepaper, where it becomes the average connected receptive field size
+ * of the columns).  The input is an image of input_w pixels per row (pixel
+ * p at x = p mod input_w, y = p div input_w; in_h = ceil(N / input_w)
+ * rows) and the columns a grid of grid_w per row (grid_h = ceil(C /
+ * grid_w) rows).  After a learning frame, over the n columns with at least
+ * one connected synapse, A = the sum of span_x + span_y, span = max - min
+ * + 1 of the connected inputs' coordinates, and
+ *   radius = max(1, floor(A (grid_w in_h + grid_h in_w) / (8 n in_w in_h))),
+ * i.e. the mean extent A / 2n times the mean grid-per-input ratio is the
+ * diameter d and the radius is (d - 1) / 2 rounded half up; with n = 0 the
+ * radius stays.  radius_dev: a device uint32 holding the radius of the
+ * first frame, updated on the stream after each learning frame (learn = 0
+ * leaves it); radii_dev [F] (may be NULL) receives the radius each frame
+ * used.  Runs one launch sequence per frame (no persistent execution).
+ * SP_EINVAL on a bad grid_w, input_w or pointer. */
+int sp_step_local_adaptive(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames,
+                           int learn, uint32_t input_w, uint32_t grid_w, uint32_t* radius_dev,
+                           int32_t* overlaps_dev, uint8_t* active_dev, uint32_t* radii_dev,
+                           void* stream);
+
 /* Adaptive video encoder (Section 3.1.2): colour frames to the pooler's
  * packed binary input.  Each frame may be reduced by an integer factor
  * (block means, rounded half up), is converted to grayscale (BT.601 luma in

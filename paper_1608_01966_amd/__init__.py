@@ -27,7 +27,7 @@ __all__ = [
     "SpError", "SpatialPooler", "synth", "sp_config_check", "sp_frame_words",
     "sp_workspace_bytes", "sp_check_state_host", "sp_create", "sp_check_state", "sp_step",
     "sp_step_plain", "sp_infer", "sp_step_many", "sp_step_many_raw", "sp_set_histogram", "sp_encode",
-    "sp_inhibit_local", "sp_step_local", "sp_step_boost", "sp_boost_state", "sp_boost_reset",
+    "sp_inhibit_local", "sp_step_local", "sp_step_local_adaptive", "sp_step_boost", "sp_boost_state", "sp_boost_reset",
     "sp_encoded_bits", "sp_step_is_persistent", "sp_step_kernel", "sp_step_local_kernel",
     "sp_step_boost_kernel", "sp_test_stall", "STEP_KERNELS", "sp_state_bytes", "sp_get_state",
     "sp_set_state", "sp_get_boost_state", "sp_set_boost_state",
@@ -263,6 +263,23 @@ def sp_step_local(h: int, cfg: dict, frames, learn: bool, grid_w: int, radius: i
                                ctypes.c_void_p(overlaps.data_ptr()) if overlaps is not None
                                else None, ctypes.c_void_p(active.data_ptr()),
                                _stream(stream)), "sp_step_local")
+
+
+def sp_step_local_adaptive(h: int, cfg: dict, frames, learn: bool, input_w: int, grid_w: int,
+                           radius, overlaps, active, radii=None, stream=None) -> None:
+    """sp_step_local with the radius adapted after each learning frame.
+    radius: int32 GPU tensor [1] (the first frame's radius in, the last
+    radius out); radii: int32 GPU tensor [F] of each frame's radius, or None."""
+    import torch
+    F = int(frames.shape[0])
+    C = cfg["num_columns"]
+    pr = _dev(radius, torch.int32, (1,), "radius")
+    pa = _dev(active, torch.uint8, (F, C), "active")
+    po = _dev(overlaps, torch.int32, (F, C), "overlaps")
+    prs = _dev(radii, torch.int32, (F,), "radii")
+    _check(lib().sp_step_local_adaptive(ctypes.c_void_p(h), ctypes.c_void_p(frames.data_ptr()), F,
+                                        int(bool(learn)), int(input_w), int(grid_w), pr, po, pa,
+                                        prs, _stream(stream)), "sp_step_local_adaptive")
 
 
 def _enc_cfg(width: int, height: int, factor: int = 1, block: int = 11, offset: int = 2):

@@ -80,6 +80,7 @@ SIGNATURES = [
     ("sp_boost_reset", ctypes.c_int, [P, P]),
     ("sp_inhibit_local", ctypes.c_int, [P, U32, U32, U32, U32, U32, P, P]),
     ("sp_step_local", ctypes.c_int, [P, P, U32, ctypes.c_int, U32, U32, P, P, P]),
+    ("sp_step_local_adaptive", ctypes.c_int, [P, P, U32, ctypes.c_int, U32, U32, P, P, P, P, P]),
     ("sp_encoded_bits", ctypes.c_size_t, [ctypes.POINTER(EncCfg)]),
     ("sp_encode", ctypes.c_int, [ctypes.POINTER(EncCfg), P, U32, P, P]),
     ("sp_step_is_persistent", ctypes.c_int, [P]),

@@ -29,6 +29,7 @@ struct sp_handle {
   uint32_t* xchg;      // [replicas][2][exchange entries] of 16 bits
   uint32_t* err;       // [1] (padded)
   uint32_t* check;     // [4]
+  uint64_t* racc;      // [2] sums of the radius adaptation (zero between frames)
   int32_t* ov_scratch; // [C]
   uint32_t* many_ovx;  // [C] tagged overlaps of the many-instance step
   uint32_t* hist;      // caller's [C] winner counts, or null
@@ -109,7 +110,7 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Workspace layout, each part 256-byte aligned.
 struct WsLayout {
-  size_t xchg, err, check, ov, many_ovx, many_dec, xloc, total;
+  size_t xchg, err, check, racc, ov, many_ovx, many_dec, xloc, total;
 };
 
 WsLayout ws_layout(const sp_config& c) {
@@ -120,7 +121,8 @@ WsLayout ws_layout(const sp_config& c) {
                                (size_t)htmsp::persistent_exchange_entries(c.num_columns),
                    256);
   l.check = align_up(l.err + sizeof(uint32_t), 256);
-  l.ov = align_up(l.check + 4 * sizeof(uint32_t), 256);
+  l.racc = align_up(l.check + 4 * sizeof(uint32_t), 256);
+  l.ov = align_up(l.racc + 2 * sizeof(uint64_t), 256);
   l.many_ovx = align_up(l.ov + sizeof(int32_t) * (size_t)c.num_columns, 256);
   // read in pairs of entries by 256-column words
   l.many_dec = align_up(l.many_ovx + sizeof(uint32_t) * align_up(c.num_columns, 256), 256);
@@ -610,6 +612,7 @@ int sp_create(const sp_config* cfg, uint32_t* idx_dev, float* perm_dev, void* st
   h->xchg = reinterpret_cast<uint32_t*>(base + l.xchg);
   h->err = reinterpret_cast<uint32_t*>(base + l.err);
   h->check = reinterpret_cast<uint32_t*>(base + l.check);
+  h->racc = reinterpret_cast<uint64_t*>(base + l.racc);
   h->ov_scratch = reinterpret_cast<int32_t*>(base + l.ov);
   h->many_ovx = reinterpret_cast<uint32_t*>(base + l.many_ovx);
   h->many_dec = reinterpret_cast<uint64_t*>(base + l.many_dec);
@@ -1103,6 +1106,44 @@ int sp_step_local(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames,
     if (e == hipSuccess && learn) e = htmsp::launch_learn_active(h->idx, h->perm, frame, act, sh, s);
     if (e != hipSuccess) return hip_fail(e, "local step launch");
   }
+  return add_histogram_active(h, active_dev, num_frames, s);
+}
+
+int sp_step_local_adaptive(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames,
+                           int learn, uint32_t input_w, uint32_t grid_w, uint32_t* radius_dev,
+                           int32_t* overlaps_dev, uint8_t* active_dev, uint32_t* radii_dev,
+                           void* stream) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  const Shape& sh = h->sh;
+  if (grid_w < 1 || grid_w > sh.C) return fail(SP_EINVAL, "grid_w=%u outside 1..C", grid_w);
+  if (input_w < 1 || input_w > sh.N)
+    return fail(SP_EINVAL, "input_w=%u outside 1..input_bits", input_w);
+  if (!radius_dev || !aligned4(radius_dev) || (radii_dev && !aligned4(radii_dev)))
+    return fail(SP_EINVAL, "radius (4-byte aligned) is required");
+  if (num_frames == 0) return ok();
+  if (!frames_dev || !active_dev || !aligned4(frames_dev) || (overlaps_dev && !aligned4(overlaps_dev)))
+    return fail(SP_EINVAL, "frames (4-byte aligned) and active are required");
+  DeviceScope ds(h->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  IdleOnExit idle{h, s};
+  note_learned(h, num_frames, learn);
+  hipError_t e = htmsp::launch_radius_adapt(h->idx, h->perm, sh, input_w, grid_w, h->racc,
+                                            radius_dev, s, true);
+  for (uint32_t t = 0; t < num_frames && e == hipSuccess; ++t) {
+    const uint32_t* frame = frames_dev + (size_t)t * sh.W;
+    int32_t* ov = overlaps_dev ? overlaps_dev + (size_t)t * sh.C : h->ov_scratch;
+    uint8_t* act = active_dev + (size_t)t * sh.C;
+    e = htmsp::launch_overlap_plain(h->idx, h->perm, frame, ov, sh, s);
+    if (e == hipSuccess)
+      e = htmsp::launch_inhibit_local(ov, 1, sh.C, grid_w, 0, sh.k, act, s, radius_dev,
+                                      radii_dev ? radii_dev + t : nullptr);
+    if (e == hipSuccess && learn) e = htmsp::launch_learn_active(h->idx, h->perm, frame, act, sh, s);
+    if (e == hipSuccess && learn)
+      e = htmsp::launch_radius_adapt(h->idx, h->perm, sh, input_w, grid_w, h->racc, radius_dev,
+                                     s);
+  }
+  if (e != hipSuccess) return hip_fail(e, "adaptive local step launch");
   return add_histogram_active(h, active_dev, num_frames, s);
 }
 

@@ -16,11 +16,16 @@
 // keeps the last b of them in registers and forms the vertical window sum;
 // one LDS row of vertical sums per output row then gives every thread its
 // horizontal window sum.  Threads of halo columns outside the image read the
-// nearest edge column, so border repetition needs no special case.  A
-// 64-lane ballot per row and wave is OR-ed into the (zeroed) output words it
-// covers, which makes any width and strip boundary correct.  Bands of one
-// frame share an XCD (block ids equal modulo 8), so the halo rows two bands
-// both read come from L2.
+// nearest edge column, so border repetition needs no special case.  When
+// the output width is a multiple of 32 (rows start on word boundaries), a
+// strip's output width is a multiple of 32 too (512 threads: 480 columns at
+// the largest window, two strips for a 960-wide frame): every wave leaves
+// its row ballot in LDS and, after the next row's barrier, a thread per
+// output word assembles and stores the word once, so each word is written
+// by one store and nothing is cleared first.  Other widths OR each wave's
+// 64-lane ballot into the (zeroed) output words it covers, which makes any
+// width and strip boundary correct.  Bands of one frame share an XCD (block
+// ids equal modulo 8), so the halo rows two bands both read come from L2.
 #include "sp_device.h"
 #include "sp_internal.h"
 
@@ -30,8 +35,16 @@ namespace {
 
 using namespace dev;
 
-constexpr uint32_t kEncThreads = 256;
+constexpr uint32_t kEncThreads = 256;       // strips OR-ed into zeroed words
+constexpr uint32_t kEncWordThreads = 512;   // strips of whole words
 constexpr uint32_t kBandRows = 64;
+
+// Output columns per strip: THREADS less the halo on each side, rounded
+// down to whole 32-bit words when WORDS.
+template <int B, int THREADS, bool WORDS>
+constexpr uint32_t strip_width() {
+  return WORDS ? (uint32_t)((THREADS - 2 * (B / 2)) & ~31) : (uint32_t)(THREADS - 2 * (B / 2));
+}
 
 __global__ __launch_bounds__(256) void k_zero(uint32_t* __restrict__ out, size_t n) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -39,14 +52,18 @@ __global__ __launch_bounds__(256) void k_zero(uint32_t* __restrict__ out, size_t
     out[i] = 0u;
 }
 
-// ONE: no reduction (factor 1), the rows' loads issued ahead.
-template <int B, bool ONE>
-__global__ __launch_bounds__(kEncThreads) void k_encode(const uint8_t* __restrict__ rgb,
-                                                        uint32_t F, EncShape e,
-                                                        uint32_t* __restrict__ out) {
+// ONE: no reduction (factor 1), the rows' loads issued ahead.  WORDS: the
+// output width is a multiple of 32 and every word is stored whole (see
+// above).
+template <int B, bool ONE, int THREADS, bool WORDS>
+__global__ __launch_bounds__(THREADS) void k_encode(const uint8_t* __restrict__ rgb,
+                                                    uint32_t F, EncShape e,
+                                                    uint32_t* __restrict__ out) {
   constexpr int R = B / 2;
-  constexpr uint32_t TW = kEncThreads - 2 * R;  // output columns per strip
-  __shared__ uint32_t vrow[2][kEncThreads];
+  constexpr uint32_t TW = strip_width<B, THREADS, WORDS>();  // output columns per strip
+  constexpr uint32_t kWaves = THREADS / kWave;
+  __shared__ uint32_t vrow[2][THREADS];
+  __shared__ uint64_t bal[2][WORDS ? kWaves : 1];
   const uint32_t strips = (e.w + TW - 1) / TW;
   const uint32_t bands = (e.h + kBandRows - 1) / kBandRows;
   const uint32_t per = 8 * strips * bands;
@@ -100,6 +117,19 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(const uint8_t* __restric
   for (int i = 0; i < B - 1; ++i) win[i + 1] = gray((uint32_t)min(max((int)y0 - R + i, 0), (int)e.h - 1));
   uint32_t* dst = out + (size_t)f * e.words;
   uint32_t buf = 0;
+  // WORDS: word j of output row `row` of this strip from the ballots in
+  // bal[b] (bit t of the concatenated ballots is thread t's column).
+  auto flush = [&](uint32_t row, uint32_t b) {
+    if constexpr (WORDS) {
+      const uint32_t j = tid;
+      if (row < y1 && j < TW / 32 && strip * TW + 32 * j < e.w) {
+        const uint32_t start = (uint32_t)R + 32 * j, q = start >> 6, o = start & 63u;
+        uint64_t v = bal[b][q] >> o;
+        if (o > 32) v |= bal[b][q + 1] << (64 - o);
+        dst[((size_t)row * e.w + strip * TW) / 32 + j] = (uint32_t)v;
+      }
+    }
+  };
   // Without reduction, the RGB bytes of the row entering the window are
   // loaded kAhead rows before they are needed, into a ring indexed by the
   // unrolled row (so that no register with a load in flight is copied);
@@ -133,9 +163,11 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(const uint8_t* __restric
 #pragma unroll
     for (int i = 0; i < B; ++i) v += wt[i] * win[i];
     vrow[buf][tid] = v;
-    // The row of vertical sums is the only thing the barrier orders: wait for
-    // LDS only, so the row loads issued ahead stay in flight across it.
+    // The row of vertical sums (and the previous row's ballots) are the only
+    // thing the barrier orders: wait for LDS only, so the row loads issued
+    // ahead stay in flight across it.
     asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    if (y > y0) flush(y - 1, buf ^ 1u);
     bool on = false;
     if (out_col && y < y1) {
       const uint32_t* vr = &vrow[buf][tid - R];
@@ -146,6 +178,11 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(const uint8_t* __restric
       on = (int)win[R] > mean - e.offset;
     }
     uint64_t bits = __ballot(on);
+    if constexpr (WORDS) {
+      if (lane == 0) bal[buf][wave] = bits;
+      buf ^= 1u;
+      continue;
+    }
     // the wave's 64 columns start at xs; output bit y * w + xs + lane
     int xs = (int)(strip * TW) - R + (int)(kWave * wave);
     if (xs < 0) {  // first strip: its left halo lanes carry no output
@@ -164,6 +201,12 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(const uint8_t* __restric
     buf ^= 1u;
   }
   }
+  if constexpr (WORDS) {
+    // the band's last row: its ballots are in bal[buf ^ 1]
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    const uint32_t rows = (y1 - y0 + kAhead - 1) / kAhead * kAhead;
+    flush(y0 + rows - 1, buf ^ 1u);
+  }
 }
 
 }  // namespace
@@ -171,24 +214,29 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(const uint8_t* __restric
 hipError_t launch_encode(const uint8_t* rgb, uint32_t F, const EncShape& e, uint32_t* out,
                          hipStream_t s) {
   if (F == 0) return hipSuccess;
-  const size_t n = (size_t)F * e.words;
-  size_t zb = (n + 255) / 256;
-  if (zb > 4096) zb = 4096;
-  hipLaunchKernelGGL(k_zero, dim3((uint32_t)zb), dim3(256), 0, s, out, n);
-  hipError_t err = hipGetLastError();
-  if (err != hipSuccess) return err;
-  const uint32_t r = e.block / 2, tw = kEncThreads - 2 * r;
-  const uint32_t strips = (e.w + tw - 1) / tw;
+  const bool words = e.w % 32 == 0;
+  if (!words) {
+    const size_t n = (size_t)F * e.words;
+    size_t zb = (n + 255) / 256;
+    if (zb > 4096) zb = 4096;
+    hipLaunchKernelGGL(k_zero, dim3((uint32_t)zb), dim3(256), 0, s, out, n);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+  }
   const uint32_t bands = (e.h + kBandRows - 1) / kBandRows;
-  const uint32_t blocks = (F + 7) / 8 * 8 * strips * bands;
-#define HTMSP_ENC(B)                                                                        \
-  case B:                                                                                   \
-    if (e.factor == 1)                                                                      \
-      hipLaunchKernelGGL((k_encode<B, true>), dim3(blocks), dim3(kEncThreads), 0, s, rgb, F, \
-                         e, out);                                                           \
-    else                                                                                    \
-      hipLaunchKernelGGL((k_encode<B, false>), dim3(blocks), dim3(kEncThreads), 0, s, rgb,  \
-                         F, e, out);                                                        \
+  auto blocks = [&](uint32_t tw) { return (F + 7) / 8 * 8 * ((e.w + tw - 1) / tw) * bands; };
+#define HTMSP_ENC_GO(B, ONE, T, WD)                                                            \
+  hipLaunchKernelGGL((k_encode<B, ONE, T, WD>), dim3(blocks(strip_width<B, T, WD>())), dim3(T), \
+                     0, s, rgb, F, e, out)
+#define HTMSP_ENC(B)                                                                  \
+  case B:                                                                             \
+    if (words) {                                                                      \
+      if (e.factor == 1) HTMSP_ENC_GO(B, true, kEncWordThreads, true);                \
+      else HTMSP_ENC_GO(B, false, kEncWordThreads, true);                             \
+    } else {                                                                          \
+      if (e.factor == 1) HTMSP_ENC_GO(B, true, kEncThreads, false);                   \
+      else HTMSP_ENC_GO(B, false, kEncThreads, false);                                \
+    }                                                                                 \
     break;
   switch (e.block) {
     HTMSP_ENC(3) HTMSP_ENC(5) HTMSP_ENC(7) HTMSP_ENC(9) HTMSP_ENC(11)
@@ -196,6 +244,7 @@ hipError_t launch_encode(const uint8_t* rgb, uint32_t F, const EncShape& e, uint
       return hipErrorInvalidValue;
   }
 #undef HTMSP_ENC
+#undef HTMSP_ENC_GO
   return hipGetLastError();
 }
 

@@ -201,7 +201,16 @@ const void* persistent_boost_kernel(uint32_t rpc, uint32_t nv, uint32_t rw);
 
 // Local inhibition (sp_local.hip): active [F][C] from overlaps [F][C].
 hipError_t launch_inhibit_local(const int32_t* ov, uint32_t F, uint32_t C, uint32_t grid_w,
-                                uint32_t radius, uint32_t n, uint8_t* active, hipStream_t s);
+                                uint32_t radius, uint32_t n, uint8_t* active, hipStream_t s,
+                                const uint32_t* radius_dev = nullptr,
+                                uint32_t* radius_out = nullptr);
+// Inhibition radius adaptation after a learning frame: the connected
+// receptive-field extents of every column summed into acc[0..1] (A, n),
+// then *radius = max(1, floor(A B / (8 n in_w in_h))) unless n == 0, and
+// acc cleared.  reset_only: only clear acc.
+hipError_t launch_radius_adapt(const uint32_t* idx, const float* perm, const Shape& sh,
+                               uint32_t in_w, uint32_t grid_w, uint64_t* acc, uint32_t* radius,
+                               hipStream_t s, bool reset_only = false);
 // Learning of one frame on the columns flagged in active[C].
 hipError_t launch_learn_active(const uint32_t* idx, float* perm, const uint32_t* frame,
                                const uint8_t* active, const Shape& sh, hipStream_t s);

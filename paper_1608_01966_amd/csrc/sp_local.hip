@@ -24,11 +24,19 @@ constexpr uint32_t kLocalLdsColumns = 16384;  // a frame's overlaps fit LDS up t
 
 // Block (frame f, columns [b * 256, b * 256 + 256)).  LDS: the whole frame's
 // overlaps when they fit, else reads from device memory.
+// `radius_dev`, when set, holds the radius instead of `radius` (the
+// adaptive step keeps it in device memory), and block 0 then records it in
+// `radius_out`, when set.
 template <bool LDS>
 __global__ __launch_bounds__(kLocalThreads) void k_inhibit_local(
     const int32_t* __restrict__ ov, uint32_t C, uint32_t grid_w, uint32_t radius, uint32_t n,
-    uint32_t col_blocks, uint8_t* __restrict__ active) {
+    uint32_t col_blocks, uint8_t* __restrict__ active, const uint32_t* __restrict__ radius_dev,
+    uint32_t* __restrict__ radius_out) {
   __shared__ int32_t s_ov[LDS ? kLocalLdsColumns : 1];
+  if (radius_dev) {
+    radius = *radius_dev;
+    if (radius_out && blockIdx.x == 0 && threadIdx.x == 0) *radius_out = radius;
+  }
   const uint32_t f = blockIdx.x / col_blocks;
   const uint32_t c = (blockIdx.x % col_blocks) * kLocalThreads + threadIdx.x;
   const int32_t* o = ov + (size_t)f * C;
@@ -77,6 +85,75 @@ __global__ __launch_bounds__(256) void k_learn_active(const uint32_t* __restrict
     const uint32_t i = min(ci[s], sh.N - 1);
     cp[s] = q_to_perm(learn_q(perm_to_q(cp[s]), input_bit(frame[i >> 5], i), sh));
   }
+}
+
+// Inhibition radius adaptation (after a learning frame, the average
+// connected receptive field of the columns carried to the column grid; the
+// rule is stated with sp_step_local_adaptive in include/sp.h).  One wave per
+// column: the extent of its connected inputs on the input image, then one
+// add of span_x + span_y and one count per column into acc = {A, n}.
+__device__ __forceinline__ uint32_t wave_min(uint32_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = min(v, (uint32_t)__shfl_xor(v, off));
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = max(v, (uint32_t)__shfl_xor(v, off));
+  return v;
+}
+
+__global__ __launch_bounds__(256) void k_radius_span(const uint32_t* __restrict__ idx,
+                                                     const float* __restrict__ perm, Shape sh,
+                                                     uint32_t in_w,
+                                                     unsigned long long* __restrict__ acc) {
+  const uint32_t c = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  const uint32_t lane = threadIdx.x % kWave;
+  if (c >= sh.C) return;  // whole wave
+  uint32_t x0 = 0xFFFFFFFFu, y0 = 0xFFFFFFFFu, x1 = 0, y1 = 0;
+  for (uint32_t s = lane; s < sh.S; s += kWave) {
+    const size_t off = (size_t)c * sh.S + s;
+    if (perm_to_q(perm[off]) < sh.theta) continue;
+    const uint32_t p = min(idx[off], sh.N - 1);
+    const uint32_t y = p / in_w, x = p - y * in_w;
+    x0 = min(x0, x);
+    x1 = max(x1, x);
+    y0 = min(y0, y);
+    y1 = max(y1, y);
+  }
+  x0 = wave_min(x0);
+  y0 = wave_min(y0);
+  x1 = wave_max(x1);
+  y1 = wave_max(y1);
+  if (lane == 0 && x0 != 0xFFFFFFFFu) {
+    atomicAdd(&acc[0], (unsigned long long)(x1 - x0 + 1) + (y1 - y0 + 1));
+    atomicAdd(&acc[1], 1ull);
+  }
+}
+
+// One thread: the new radius from acc (unchanged when no column has a
+// connected synapse), floor(A B / D) with the 128-bit product divided by
+// shifts and subtractions; then acc is cleared for the next frame.
+__global__ void k_radius_update(unsigned long long* __restrict__ acc, uint32_t* __restrict__ radius,
+                                uint64_t B, uint64_t in_area8, uint32_t reset_only) {
+  const unsigned long long A = acc[0], n = acc[1];
+  acc[0] = 0;
+  acc[1] = 0;
+  if (reset_only || n == 0) return;
+  const unsigned __int128 num = (unsigned __int128)A * B;
+  const unsigned __int128 den = (unsigned __int128)in_area8 * n;
+  unsigned __int128 rem = 0;
+  uint64_t q = 0;
+  for (int bit = 127; bit >= 0; --bit) {
+    rem = (rem << 1) | (unsigned __int128)((num >> bit) & 1u);
+    if (rem >= den) {
+      rem -= den;
+      if (bit < 64) q |= 1ull << bit;
+      else q = 0xFFFFFFFFFFFFFFFFull;  // cannot happen for valid shapes; saturate
+    }
+  }
+  *radius = q < 1 ? 1u : (q > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)q);
 }
 
 // Persistent learning step with local inhibition: F frames in one
@@ -291,16 +368,36 @@ __global__ __launch_bounds__(kPersistWaves * kWave) void k_sp_persistent_local(L
 }  // namespace
 
 hipError_t launch_inhibit_local(const int32_t* ov, uint32_t F, uint32_t C, uint32_t grid_w,
-                                uint32_t radius, uint32_t n, uint8_t* active, hipStream_t s) {
+                                uint32_t radius, uint32_t n, uint8_t* active, hipStream_t s,
+                                const uint32_t* radius_dev, uint32_t* radius_out) {
   if (F == 0) return hipSuccess;
   const uint32_t col_blocks = (C + kLocalThreads - 1) / kLocalThreads;
   const dim3 grid(F * col_blocks);
   if (C <= kLocalLdsColumns)
     hipLaunchKernelGGL(k_inhibit_local<true>, grid, dim3(kLocalThreads), 0, s, ov, C, grid_w,
-                       radius, n, col_blocks, active);
+                       radius, n, col_blocks, active, radius_dev, radius_out);
   else
     hipLaunchKernelGGL(k_inhibit_local<false>, grid, dim3(kLocalThreads), 0, s, ov, C, grid_w,
-                       radius, n, col_blocks, active);
+                       radius, n, col_blocks, active, radius_dev, radius_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_radius_adapt(const uint32_t* idx, const float* perm, const Shape& sh,
+                               uint32_t in_w, uint32_t grid_w, uint64_t* acc, uint32_t* radius,
+                               hipStream_t s, bool reset_only) {
+  const uint64_t in_h = ((uint64_t)sh.N + in_w - 1) / in_w;
+  const uint64_t grid_h = ((uint64_t)sh.C + grid_w - 1) / grid_w;
+  const uint64_t B = (uint64_t)grid_w * in_h + grid_h * in_w;
+  const uint64_t area8 = 8ull * in_w * in_h;
+  unsigned long long* a = reinterpret_cast<unsigned long long*>(acc);
+  if (!reset_only) {
+    hipLaunchKernelGGL(k_radius_span, dim3((sh.C + 3) / 4), dim3(256), 0, s, idx, perm, sh, in_w,
+                       a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_radius_update, dim3(1), dim3(1), 0, s, a, radius, B, area8,
+                     reset_only ? 1u : 0u);
   return hipGetLastError();
 }
 

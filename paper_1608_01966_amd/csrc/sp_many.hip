@@ -382,7 +382,14 @@ __global__ __launch_bounds__(kManyThreads, 2) void k_sp_many(ManyArgs a) {
   // ---- tile workgroup ----
   // Wave 0 looks at every tile at once (lane j: tile j) and takes the first
   // ready one at or after `rr`, so that no tile is passed over for long.
+  // The decision words it looks at were loaded while the previous tile step
+  // ran (issued with that step's state loads, so the two latencies overlap);
+  // a word loaded before its decision was published only makes a tile look
+  // not ready yet (readiness is an exact tag match), and when no tile looks
+  // ready the words are loaded again.
   uint32_t rr = 0, spins = 0;
+  uint64_t dpre = 0;
+  bool have = false;
   while (true) {
     if (wave == 0) {
       uint32_t status = 3, pick = 0, T = 0, clast1 = 0;  // 3: nothing ready yet
@@ -392,8 +399,9 @@ __global__ __launch_bounds__(kManyThreads, 2) void k_sp_many(ManyArgs a) {
         const uint32_t j = lane < nt ? lane : 0u;
         const uint32_t t = s_next[j];
         const bool live = lane < nt && t <= s_inst[j].F;
-        uint64_t d = 0;
-        if (live && t > 0) d = load_word(gbl(s_inst[j].dec));
+        uint64_t d = dpre;
+        if (!have) d = (live && t > 0) ? load_word(gbl(s_inst[j].dec)) : 0ull;
+        have = false;
         const bool ready =
             live && (t == 0 || (uint32_t)(d >> 48) == ((s_inst[j].step_base + t) & 0xFFFFu));
         const uint64_t lm = __ballot(live), rm = __ballot(ready);
@@ -435,6 +443,15 @@ __global__ __launch_bounds__(kManyThreads, 2) void k_sp_many(ManyArgs a) {
     if (status == 0) {
       const uint32_t j = s_pick[0];
       const ManyTask& task = s_task[j];
+      if (wave == 0) {
+        // the decisions the next pick looks at (the picked tile's own word is
+        // still that of its current step, so it looks not ready, as it is)
+        const uint32_t jj = lane < nt ? lane : 0u;
+        const uint32_t tt = s_next[jj];
+        dpre = (lane < nt && tt > 0 && tt <= s_inst[jj].F) ? load_word(gbl(s_inst[jj].dec))
+                                                            : 0ull;
+        have = true;
+      }
       tile_step<ALIGNED>(a, s_inst[j], task.c0, task.c1, s_next[j], j, L, s_pick[1], s_pick[2]);
       // every thread has read s_next[j] and s_pick before tile_step's barrier
       if (tid == 0) s_next[j] += 1;

@@ -177,6 +177,25 @@ class Server:
             self.peak_used = max(self.peak_used, self.used)
             self.admit_waits.append(now - float(self.arr[self.off[i] + self.next[i]]))
 
+    def preadmit(self):
+        """Admits, before the clock starts, every stream that fits the budget
+        in order of first arrival (streams already connected when their
+        frames start to arrive); the rest are admitted as usual."""
+        order = np.argsort(np.array([s.arrivals[0] if len(s.arrivals) else np.inf
+                                     for s in self.specs]), kind="stable")
+        for i in order:
+            i = int(i)
+            if self.finished[i] or self.resident[i]:
+                continue
+            need = int(self.need[i])
+            if self.used + need > self.budget:
+                break
+            self.handles[i] = self.backend.open(i, self.specs[i], None)
+            self.resident[i] = True
+            self.admitted_at[i] = 0.0
+            self.used += need
+            self.peak_used = max(self.peak_used, self.used)
+
     def _make_room(self, need: int, now: float):
         cand = np.flatnonzero(self.resident & (self.busy == 0) &
                               (now - self.admitted_at >= self.quantum))

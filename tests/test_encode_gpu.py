@@ -27,6 +27,10 @@ def _check(rgb, factor, block, offset):
     (64, 2, 1, 7, 5), (65, 40, 1, 9, 2), (130, 77, 2, 11, 2), (241, 135, 3, 5, 1),
     (500, 301, 1, 11, 2), (960, 540, 4, 11, 2), (1921, 37, 1, 3, 2), (4096, 20, 1, 11, 2),
     (8192, 9, 2, 5, 2),
+    # output widths that are whole words (each word stored once): one strip,
+    # several strips with a partial last one, several bands with ragged ends
+    (32, 70, 1, 11, 2), (128, 33, 1, 3, 2), (992, 13, 1, 11, 2), (1024, 66, 2, 5, 2),
+    (64, 130, 1, 9, -4), (1920, 200, 2, 7, 1),
 ])
 def test_shapes(W, H, factor, block, offset):
     rgb = synth.rgb_frames(synth.rng(W * 7 + H, 6), 3, W, H)

@@ -159,3 +159,46 @@ def test_rejects_bad_arguments():
         args.update(kw)
         with pytest.raises(sp.SpError):
             sp.sp_inhibit_local(ov, **args)
+
+
+ADAPT = [
+    # (name, N, in_w, C, S, grid_w, radius0, n, frames, density)
+    ("960x540_32x32_grid", 960 * 540, 960, 1024, 128, 32, 8, 3, 16, 0.05),
+    ("ragged_grid_and_rows", 37 * 23 - 11, 37, 301, 40, 17, 3, 4, 14, 0.2),
+    ("one_row_grid", 4000, 80, 500, 64, 500, 80, 6, 10, 0.1),
+]
+
+
+@pytest.mark.parametrize("case", ADAPT, ids=[a[0] for a in ADAPT])
+@pytest.mark.parametrize("learn", [True, False])
+def test_step_local_adaptive(case, learn):
+    """The radius adapted after every learning frame (reading L5): overlaps,
+    active columns, permanences, every frame's radius and the final radius
+    against the oracle."""
+    import torch
+    name, N, in_w, C, S, grid_w, r0, n, F, d = case
+    cfg = synth.sp_config(N, C, S, 2, n)
+    blobs = name.startswith("960")
+    w = synth.random_instance(61, cfg, F, density=d,
+                              shape=(960, 540) if blobs else None, blobs=blobs)
+    e_ov, e_act, e_perm, e_radii, e_r = oracle.run_local_adaptive(
+        cfg, w.idx, w.perm, w.frames, in_w, grid_w, r0, n, learn=learn)
+    pool = sp.SpatialPooler(cfg, w.idx, w.perm)
+    frames = torch.from_numpy(np.ascontiguousarray(w.frames).view(np.int32)).cuda()
+    ov = torch.full((F, C), -1, dtype=torch.int32, device="cuda")
+    act = torch.full((F, C), 7, dtype=torch.uint8, device="cuda")
+    radius = torch.tensor([r0], dtype=torch.int32, device="cuda")
+    radii = torch.zeros(F, dtype=torch.int32, device="cuda")
+    half = F // 2
+    for a0, a1 in ((0, half), (half, F)):
+        sp.sp_step_local_adaptive(pool.handle, cfg, frames[a0:a1], learn, in_w, grid_w, radius,
+                                  ov[a0:a1], act[a0:a1], radii[a0:a1])
+    pool.sync()
+    assert np.array_equal(ov.cpu().numpy(), e_ov)
+    assert np.array_equal(act.cpu().numpy(), e_act)
+    assert np.array_equal(pool.perm.cpu().numpy().astype(np.float64), e_perm)
+    assert np.array_equal(radii.cpu().numpy().astype(np.uint32), e_radii)
+    assert int(radius.item()) == e_r
+    if learn and name != "one_row_grid":
+        assert len(set(e_radii.tolist())) > 1, "the radius should move on this workload"
+    pool.close()

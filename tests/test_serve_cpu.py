@@ -195,3 +195,18 @@ def test_streams_live_for_the_whole_window_by_default():
     for s in specs:
         assert s.arrivals[0] < 1.0 and s.arrivals[-1] > 9.0
         assert 200 < len(s.arrivals) < 400
+
+
+def test_preadmit_within_budget():
+    specs = small_streams(10, seed=9)
+    clock = FakeClock()
+    fr = pool()
+    be = OracleBackend(fr, specs, clock)
+    need = [be.stream_bytes(s) for s in specs]
+    budget = sum(need) - min(need)   # all but (at least) one stream
+    srv = serve.Server(be, specs, budget_bytes=budget)
+    srv.preadmit()
+    assert 0 < srv.resident.sum() < len(specs) and srv.used <= budget
+    srv.run(clock)
+    assert srv.finished.all() and srv.peak_used <= budget
+    check_alone(specs, fr, be)

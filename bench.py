@@ -802,7 +802,7 @@ def bench_serve(args, torch, sp, synth):
                "peak_resident_bytes": srv.peak_used, "budget_bytes": srv.budget,
                "state_bytes_all_streams": total,
                "evictions": srv.evictions, "readmissions": srv.readmissions,
-               "max_admission_wait_ms": float(max(srv.admit_waits) * 1e3),
+               "max_admission_wait_ms": float(max(srv.admit_waits, default=0.0) * 1e3),
                "algorithmic_bytes": abytes, "achieved_GBps": achieved}
         del srv, be
         torch.cuda.synchronize()

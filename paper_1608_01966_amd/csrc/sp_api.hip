@@ -116,7 +116,7 @@ struct WsLayout {
 WsLayout ws_layout(const sp_config& c) {
   WsLayout l;
   l.xchg = 0;
-  l.err = align_up(l.xchg + sizeof(uint16_t) * 2 * htmsp::kPersistMaxReplicas *
+  l.err = align_up(l.xchg + sizeof(uint16_t) * 2 * htmsp::kPersistReplicas *
                                htmsp::persistent_exchange_arrays() *
                                (size_t)htmsp::persistent_exchange_entries(c.num_columns),
                    256);

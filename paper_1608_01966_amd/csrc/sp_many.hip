@@ -91,6 +91,8 @@ struct TileLds {
   uint32_t cnt[kTileColumns];                 // raw overlap counts of the step
   uint16_t prev[kMaxTileSlots][kTileColumns];  // each tile's published overlaps of the last step
 };
+// a top-k workgroup reuses it for its waves' winner bitmaps
+static_assert(sizeof(TileLds) >= 4 * 2 * kManyNV * 8 * sizeof(uint32_t), "top-k bitmaps");
 
 // Step t of tile task `slot` of this workgroup, whole workgroup, once the
 // scheduler has seen the instance's decision of step t - 1 (T, last tied
@@ -206,11 +208,14 @@ __device__ void tile_step(const ManyArgs& a, const ManyInst& in, uint32_t c0, ui
 // the global top-k, writes the outputs and publishes the decision.  Lane l
 // holds columns u * 256 + 4l + q (q < 4) as the 16-bit fields of ev[u].
 // Registers are kept to ev[] plus per-word temporaries past the first
-// collection pass, and the winners are selected word by word while they are
-// written.
+// collection pass; the winners are ranked through bitmaps in the wave's LDS
+// `bm` (2 kManyNV * 8 words).  Kept out of line: inlined, the compiler
+// schedules its threshold search for registers that the tile path then
+// pays for in occupancy.
 // Returns false, having changed nothing, while some overlap of step t is
 // not yet published.
-__device__ bool topk_try(ManyInst& in, uint32_t t, uint32_t lane) {
+__device__ __attribute__((noinline)) bool topk_try(ManyInst& in, uint32_t t, uint32_t lane,
+                                                   uint32_t* bm) {
   const Shape& sh = in.sh;
   const uint32_t tag = (in.step_base + t + 1) & 0xFFFFu;
   // a stalled instance (failure-path tests) waits for a tag no tile writes
@@ -259,48 +264,65 @@ __device__ bool topk_try(ManyInst& in, uint32_t t, uint32_t lane) {
   const uint32_t nsel = T ? sh.k : c_hi;
   if (T) in.guess = T;
 
-  // Winners word by word: every field above T, and the first `need` fields
-  // equal to T in column order; ranks by prefix counts over the lanes.
+  // Winners in column order: every field above T, and the first `need`
+  // fields equal to T.  The two field sets go into bitmaps of C bits in this
+  // wave's LDS (bm: gt then eq, 128 words each); lane l then owns columns
+  // 64 l .. 64 l + 63 (two words of each), takes its share of the ties and
+  // writes its winners at their rank, two prefix counts over the lanes.
   HTMSP_G int32_t* wrow = gbl(in.win_out + (size_t)t * sh.k);
   HTMSP_G int32_t* ovrow = in.ov_out ? gbl(in.ov_out + (size_t)t * sh.C) : nullptr;
   HTMSP_G uint32_t* hist = in.hist ? gbl(in.hist) : nullptr;
   const uint64_t k_gt = (uint64_t)(0x8000u - (T + 1)) * kOnes16;
   const uint64_t k_ge = (uint64_t)(0x8000u - T) * kOnes16;
-  uint32_t eq_before = 0, sel_before = 0, clast1 = 0;
+  uint32_t* gtm = bm;
+  uint32_t* eqm = bm + kManyNV * 8;
+  for (uint32_t i = lane; i < kManyNV * 8; i += kWave) {
+    gtm[i] = 0;
+    eqm[i] = 0;
+  }
+  // the four field flags (bits 15, 31, 47, 63) of a word as a nibble
+  auto nibble = [](uint64_t m) {
+    return (uint32_t)(((m >> 15) & 1u) | ((m >> 30) & 2u) | ((m >> 45) & 4u) | ((m >> 60) & 8u));
+  };
 #pragma unroll
   for (uint32_t u = 0; u < kManyNV; ++u) {
     if (u < nv) {
       const uint64_t gt = (ev[u] + k_gt) & kHighBits;
       const uint64_t eq = T ? (((ev[u] + k_ge) & kHighBits) & ~gt) : 0ull;
-      const uint32_t neq = (uint32_t)__popcll(eq);
-      const uint32_t pre = eq_before + wave_prefix<3>(neq, lane);
-      uint32_t keep = need > pre ? need - pre : 0u;
-      uint64_t take = 0;
+      // columns u * 256 + 4 l + q: word 8 u + l / 8, bits 4 (l mod 8) + q
+      const uint32_t w = u * 8 + lane / 8, sft = 4 * (lane % 8);
+      const uint32_t ng = nibble(gt), ne = nibble(eq);
+      if (ng) atomicOr(&gtm[w], ng << sft);
+      if (ne) atomicOr(&eqm[w], ne << sft);
+      if (ovrow) {
 #pragma unroll
-      for (uint32_t q = 0; q < 4; ++q) {
-        const uint64_t bit = eq & (0x8000ull << (16 * q));
-        const bool use = bit != 0ull && keep > 0;
-        take |= use ? bit : 0ull;
-        keep -= use ? 1u : 0u;
-      }
-      eq_before += wave_count<3>(neq);
-      const uint64_t sel = gt | take;
-      const uint32_t n = (uint32_t)__popcll(sel);
-      uint32_t pos = sel_before + wave_prefix<3>(n, lane);
-#pragma unroll
-      for (uint32_t q = 0; q < 4; ++q) {
-        const uint32_t c = u * 4 * kWave + 4 * lane + q;
-        if (sel & (0x8000ull << (16 * q))) {
-          wrow[pos] = (int32_t)c;
-          ++pos;
-          // this wave is the instance's only histogram writer in the launch
-          if (hist) hist[c] += 1u;
+        for (uint32_t q = 0; q < 4; ++q) {
+          const uint32_t c = u * 4 * kWave + 4 * lane + q;
+          if (c < sh.C) ovrow[c] = (int32_t)((ev[u] >> (16 * q)) & 0xFFFFu);
         }
-        if (take & (0x8000ull << (16 * q))) clast1 = max(clast1, c + 1);
-        if (ovrow && c < sh.C) ovrow[c] = (int32_t)((ev[u] >> (16 * q)) & 0xFFFFu);
       }
-      sel_before += wave_count<3>(n);
     }
+  }
+  const uint64_t gmask = (uint64_t)gtm[2 * lane] | ((uint64_t)gtm[2 * lane + 1] << 32);
+  uint64_t emask = (uint64_t)eqm[2 * lane] | ((uint64_t)eqm[2 * lane + 1] << 32);
+  const uint32_t neq = (uint32_t)__popcll(emask);
+  const uint32_t eq_pre = wave_prefix<7>(neq, lane);
+  uint32_t keep = need > eq_pre ? min(need - eq_pre, neq) : 0u;
+  uint64_t take = 0;
+  for (; keep > 0; --keep) {
+    const uint64_t low = emask & (~emask + 1ull);
+    take |= low;
+    emask ^= low;
+  }
+  uint32_t clast1 = take ? 64 * lane + 64 - (uint32_t)__clzll((long long)take) : 0u;
+  uint64_t sel = gmask | take;
+  uint32_t pos = wave_prefix<7>((uint32_t)__popcll(sel), lane);
+  while (sel) {
+    const uint32_t c = 64 * lane + (uint32_t)__ffsll((long long)sel) - 1;
+    wrow[pos++] = (int32_t)c;
+    // this wave is the instance's only histogram writer in the launch
+    if (hist) hist[c] += 1u;
+    sel &= sel - 1ull;
   }
   for (uint32_t i = nsel + lane; i < sh.k; i += kWave) wrow[i] = -1;
 #pragma unroll
@@ -358,7 +380,7 @@ __global__ __launch_bounds__(kManyThreads, 2) void k_sp_many(ManyArgs a) {
         const uint32_t t = s_next[j];
         if (t >= s_inst[j].F) continue;
         all_done = false;
-        if (topk_try(s_inst[j], t, lane)) {
+        if (topk_try(s_inst[j], t, lane, reinterpret_cast<uint32_t*>(&L) + wave * kManyNV * 16)) {
           s_next[j] = t + 1;  // every lane: each keeps its own view of the slot exact
           progress = true;
         }

@@ -122,7 +122,9 @@ def copy_peak(torch, mib: int = 1024, reps: int = 5) -> float:
     `mib` MiB buffer, best of `reps`: the HBM bandwidth a plain streaming
     kernel reaches on this device, measured in the same run."""
     n = mib * (1 << 20) // 4
-    src = torch.ones(n, dtype=torch.int32, device="cuda")
+    # (contents do not matter; no fill kernel, which the memory-counter
+    # calibration would take for its copy)
+    src = torch.empty(n, dtype=torch.int32, device="cuda")
     dst = torch.empty_like(src)
     dst.copy_(src)
     best = float("inf")

@@ -105,3 +105,23 @@ def test_inference_modes_are_distinct_constants():
     L = _native.lib()
     # mode is checked after the handle: a NULL handle fails first
     assert L.sp_infer(None, None, 0, 7, None, None, None) == sp.SP_EINVAL
+
+
+def test_adaptive_local_step_and_raw_many_without_a_handle():
+    L = _native.lib()
+    r = (ctypes.c_uint32 * 1)()
+    assert L.sp_step_local_adaptive(None, None, 0, 1, 8, 4, r, None, None, None, None) == \
+        sp.SP_EINVAL
+    assert "NULL" in sp.sp_last_error()
+    # no handles: nothing to step
+    # (stream 0: the null stream, named without touching a device)
+    sp.sp_step_many_raw(np.zeros(0, np.uint64), np.zeros(0, np.uint64), np.zeros(0, np.uint32),
+                        True, None, np.zeros(0, np.uint64), stream=0)
+    with pytest.raises(ValueError):
+        sp.sp_step_many_raw(np.zeros(2, np.uint64), np.zeros(1, np.uint64),
+                            np.zeros(2, np.uint32), True, None, np.zeros(2, np.uint64), stream=0)
+    # a NULL handle in the array is rejected on the host
+    with pytest.raises(sp.SpError) as e:
+        sp.sp_step_many_raw(np.zeros(1, np.uint64), np.zeros(1, np.uint64),
+                            np.ones(1, np.uint32), True, None, np.zeros(1, np.uint64), stream=0)
+    assert e.value.code == sp.SP_EINVAL

@@ -114,30 +114,38 @@ __device__ __forceinline__ uint32_t wave_prefix(uint32_t v, uint32_t lane) {
 // Field masks of the winners among all columns of one frame: every field
 // above T, and the first `need` fields equal to T in column order (word u,
 // lane l, field q is column u*256 + 4*l + q).  T == 0 selects every
-// positive field.
+// positive field.  T and need are the same in every lane, so the words
+// before the one where the ties run out take all their ties, the words after
+// it none, and only that one word ranks its ties across the wave.  Within a
+// lane, (eq >> 15) * kOnes16 holds in each field the number of tied fields up
+// to and including it, which the field-wise compare keeps to `keep`.
 template <int NV>
 __device__ __forceinline__ void select_all(const uint64_t (&ev)[NV], uint32_t T, uint32_t need,
                                            uint32_t lane, uint64_t (&fm)[NV]) {
+  T = __builtin_amdgcn_readfirstlane(T);
+  need = __builtin_amdgcn_readfirstlane(need);
   const uint64_t k_gt = (uint64_t)(0x8000u - (T + 1)) * kOnes16;
   const uint64_t k_ge = (uint64_t)(0x8000u - T) * kOnes16;
   uint32_t before = 0;  // fields equal to T in earlier words, whole wave
 #pragma unroll
   for (int u = 0; u < NV; ++u) {
     const uint64_t gt = (ev[u] + k_gt) & kHighBits;
-    const uint64_t eq = T ? (((ev[u] + k_ge) & kHighBits) & ~gt) : 0ull;
-    const uint32_t n = (uint32_t)__popcll(eq);
-    const uint32_t pre = before + wave_prefix<3>(n, lane);
-    uint32_t keep = need > pre ? need - pre : 0u;
     uint64_t take = 0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const uint64_t bit = eq & (0x8000ull << (16 * q));
-      const bool use = bit != 0ull && keep > 0;
-      take |= use ? bit : 0ull;
-      keep -= use ? 1u : 0u;
+    if (T != 0 && before < need) {
+      const uint64_t eq = ((ev[u] + k_ge) & kHighBits) & ~gt;
+      const uint32_t n = (uint32_t)__popcll(eq);
+      const uint32_t tot = wave_count<3>(n);
+      if (before + tot <= need) {
+        take = eq;
+      } else {
+        const uint32_t pre = before + wave_prefix<3>(n, lane);
+        const uint32_t keep = need > pre ? min(need - pre, 4u) : 0u;
+        const uint64_t cum = (eq >> 15) * kOnes16;
+        take = eq & ~((cum + (uint64_t)(0x7FFFu - keep) * kOnes16) & kHighBits);
+      }
+      before += tot;
     }
     fm[u] = ((gt | take) >> 15) * 0xFFFFull;
-    before += wave_count<3>(n);
   }
 }
 

@@ -192,6 +192,32 @@ __device__ __forceinline__ bool own_wins(const uint64_t (&ev)[NV], uint32_t v, b
   return gt || (eq && eqb + (uint32_t)__popcll(eqm & lanemask_lt(lane)) < need);
 }
 
+// Whether column c_begin + lane is selected in the field masks fm of
+// select_all.  A wave's CPW columns start at a multiple of CPW (<= 16), so
+// they lie in one 256-column block (one word index u for the wave); up to
+// four of them share one lane's word, which is then read as a scalar.
+template <int NV, uint32_t CPW>
+__device__ __forceinline__ bool own_selected(const uint64_t (&fm)[NV], uint32_t lane,
+                                             uint32_t c_begin) {
+  const uint32_t ub = __builtin_amdgcn_readfirstlane(c_begin >> 8);
+  uint64_t w = fm[0];
+#pragma unroll
+  for (int u = 1; u < NV; ++u) w = (uint32_t)u == ub ? fm[u] : w;
+  const uint32_t c = c_begin + lane;
+  uint32_t lo, hi;
+  if constexpr (CPW <= 4) {
+    const uint32_t src = __builtin_amdgcn_readfirstlane((c_begin >> 2) & 63u);
+    lo = __builtin_amdgcn_readlane((uint32_t)w, src);
+    hi = __builtin_amdgcn_readlane((uint32_t)(w >> 32), src);
+  } else {
+    const int src = (int)((c >> 2) & 63u);
+    lo = (uint32_t)__shfl((int)(uint32_t)w, src);
+    hi = (uint32_t)__shfl((int)(uint32_t)(w >> 32), src);
+  }
+  const uint64_t x = ((uint64_t)hi << 32) | lo;
+  return ((x >> (16 * (c & 3u))) & 1ull) != 0ull;
+}
+
 // What one frame leaves for its deferred outputs.
 struct FrameResult {
   uint32_t T, need, nsel, ov;
@@ -475,13 +501,17 @@ __global__ __launch_bounds__(kPersistWaves * kWave) void k_sp_persistent_w(Persi
       r0.need = T0 ? sh.k - c_hi : 0u;
       r0.nsel = T0 ? sh.k : c_hi;
       r0.ov = my0;
-      r0.sel = own_wins(ev0, my0, mine, T0, r0.need, lane, c_begin);
       if (T0) guess = T0;
 
-      // Frame t + 1: every column's overlap given frame t's winners.
+      // Frame t + 1: every column's overlap given frame t's winners (whose
+      // field masks also give the own columns' frame-t result).
+      if (!two) r0.sel = own_wins(ev0, my0, mine, T0, r0.need, lane, c_begin);
       if (two) {
         uint64_t fm[NV];
         select_all(ev0, T0, r0.need, lane, fm);
+        // (read in every lane: the word it reads lives in another lane)
+        const bool own0 = own_selected<NV, CPW>(fm, lane, c_begin);
+        r0.sel = mine && own0;
 #pragma unroll
         for (int u = 0; u < NV; ++u)
           ev1[u] = ((vL[u] & ~fm[u]) | (vW[u] & fm[u])) & kFieldBits;

@@ -61,11 +61,19 @@ __device__ __forceinline__ uint32_t lds_acquire(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// c added to each of the four 16-bit fields of w, where no field sum
+// reaches 2^16: nothing carries between fields, so the two 32-bit halves add
+// on their own (two full-rate adds, not a 64-bit multiply-add).
+__device__ __forceinline__ uint64_t field_add(uint64_t w, uint32_t c) {
+  const uint32_t cc = c * 0x10001u;
+  return ((uint64_t)((uint32_t)(w >> 32) + cc) << 32) | (uint32_t)((uint32_t)w + cc);
+}
+
 // Fields of w (four 16-bit fields holding values < 2^14) that are >= x,
 // for 1 <= x <= 2^14: field + 0x8000 - x reaches bit 15 exactly when
 // field >= x, and never carries into the next field.
 __device__ __forceinline__ uint32_t fields_ge(uint64_t w, uint32_t x, uint64_t keep) {
-  return (uint32_t)__popcll((w + (uint64_t)(0x8000u - x) * kOnes16) & keep);
+  return (uint32_t)__popcll(field_add(w, 0x8000u - x) & keep);
 }
 
 // Sum over the wave of per-lane counts below 2^BITS, one ballot per bit.
@@ -101,6 +109,24 @@ __device__ __forceinline__ uint32_t count_ge_before(const uint64_t (&ev)[NV], ui
   return wave_count<ilog2(4 * NV) + 1>(n);
 }
 
+// Columns below c_end whose overlap equals x (1 <= x < 2^14): fields >= x
+// and not >= x + 1, counted in one wave sum.
+template <int NV>
+__device__ __forceinline__ uint32_t count_eq_before(const uint64_t (&ev)[NV], uint32_t x,
+                                                    uint32_t lane, uint32_t c_end) {
+  uint32_t n = 0;
+#pragma unroll
+  for (int u = 0; u < NV; ++u) {
+    const uint32_t cb = (uint32_t)u * 4 * kWave + 4 * lane;
+    const uint32_t nin = c_end > cb ? min(4u, c_end - cb) : 0u;
+    const uint64_t keep = nin >= 4 ? kHighBits : (((1ull << (16 * nin)) - 1ull) & kHighBits);
+    const uint64_t ge = field_add(ev[u], 0x8000u - x);
+    const uint64_t gt = field_add(ev[u], 0x7FFFu - x);
+    n += (uint32_t)__popcll(ge & ~gt & keep);
+  }
+  return wave_count<ilog2(4 * NV) + 1>(n);
+}
+
 // Exclusive prefix over lanes of per-lane counts below 2^BITS.
 template <int BITS>
 __device__ __forceinline__ uint32_t wave_prefix(uint32_t v, uint32_t lane) {
@@ -124,15 +150,13 @@ __device__ __forceinline__ void select_all(const uint64_t (&ev)[NV], uint32_t T,
                                            uint32_t lane, uint64_t (&fm)[NV]) {
   T = __builtin_amdgcn_readfirstlane(T);
   need = __builtin_amdgcn_readfirstlane(need);
-  const uint64_t k_gt = (uint64_t)(0x8000u - (T + 1)) * kOnes16;
-  const uint64_t k_ge = (uint64_t)(0x8000u - T) * kOnes16;
   uint32_t before = 0;  // fields equal to T in earlier words, whole wave
 #pragma unroll
   for (int u = 0; u < NV; ++u) {
-    const uint64_t gt = (ev[u] + k_gt) & kHighBits;
+    const uint64_t gt = field_add(ev[u], 0x7FFFu - T) & kHighBits;
     uint64_t take = 0;
     if (T != 0 && before < need) {
-      const uint64_t eq = ((ev[u] + k_ge) & kHighBits) & ~gt;
+      const uint64_t eq = (field_add(ev[u], 0x8000u - T) & kHighBits) & ~gt;
       const uint32_t n = (uint32_t)__popcll(eq);
       const uint32_t tot = wave_count<3>(n);
       if (before + tot <= need) {
@@ -141,7 +165,7 @@ __device__ __forceinline__ void select_all(const uint64_t (&ev)[NV], uint32_t T,
         const uint32_t pre = before + wave_prefix<3>(n, lane);
         const uint32_t keep = need > pre ? min(need - pre, 4u) : 0u;
         const uint64_t cum = (eq >> 15) * kOnes16;
-        take = eq & ~((cum + (uint64_t)(0x7FFFu - keep) * kOnes16) & kHighBits);
+        take = eq & ~(field_add(cum, 0x7FFFu - keep) & kHighBits);
       }
       before += tot;
     }

@@ -272,8 +272,6 @@ __device__ __attribute__((noinline)) bool topk_try(ManyInst& in, uint32_t t, uin
   HTMSP_G int32_t* wrow = gbl(in.win_out + (size_t)t * sh.k);
   HTMSP_G int32_t* ovrow = in.ov_out ? gbl(in.ov_out + (size_t)t * sh.C) : nullptr;
   HTMSP_G uint32_t* hist = in.hist ? gbl(in.hist) : nullptr;
-  const uint64_t k_gt = (uint64_t)(0x8000u - (T + 1)) * kOnes16;
-  const uint64_t k_ge = (uint64_t)(0x8000u - T) * kOnes16;
   uint32_t* gtm = bm;
   uint32_t* eqm = bm + kManyNV * 8;
   for (uint32_t i = lane; i < kManyNV * 8; i += kWave) {
@@ -287,8 +285,8 @@ __device__ __attribute__((noinline)) bool topk_try(ManyInst& in, uint32_t t, uin
 #pragma unroll
   for (uint32_t u = 0; u < kManyNV; ++u) {
     if (u < nv) {
-      const uint64_t gt = (ev[u] + k_gt) & kHighBits;
-      const uint64_t eq = T ? (((ev[u] + k_ge) & kHighBits) & ~gt) : 0ull;
+      const uint64_t gt = field_add(ev[u], 0x7FFFu - T) & kHighBits;
+      const uint64_t eq = T ? ((field_add(ev[u], 0x8000u - T) & kHighBits) & ~gt) : 0ull;
       // columns u * 256 + 4 l + q: word 8 u + l / 8, bits 4 (l mod 8) + q
       const uint32_t w = u * 8 + lane / 8, sft = 4 * (lane % 8);
       const uint32_t ng = nibble(gt), ne = nibble(eq);

@@ -117,6 +117,17 @@ def test_largest_instances():
     check(ws)
 
 
+def test_input_sizes_from_4m_pixels_down():
+    """One launch over a 4M-pixel input, one-synapse columns (the widest
+    tiles), the 960x540 input and an input that is not a whole number of
+    four-word groups."""
+    ws = [synth.random_instance(90, synth.sp_config(1 << 22, 300, 40, 2, 12), 5, 0.05),
+          synth.random_instance(91, synth.sp_config(5000, 700, 1, 0, 30), 5, 0.3),
+          synth.random_instance(92, synth.sp_config(33007, 512, 96, 3, 20), 5, 0.1),
+          synth.random_instance(93, synth.sp_config(960 * 540, 256, 64, 4, 10), 5, 0.05)]
+    check(ws)
+
+
 def test_multi_workload_subset():
     """The 64-instance workload's instances, 12 steps each, all compared."""
     check(synth.workload_multi(64, 12))

@@ -641,7 +641,7 @@ def bench_local(args, torch, sp, synth):
     n_act = int(act.sum().item())
     abytes = F * (frame_bytes(cfg) + 8 * C * S + 4 * C + C) + 12 * S * n_act
     achieved = abytes / (call_ms * 1e-3) / 1e9
-    kname = pool.local_kernel
+    kname = pool.local_kernel_for(1024, 80)
     traffic, traffic_bytes = (None, None)
     if kname != "plain" and F == 1000:
         traffic, traffic_bytes = measured_traffic(f"{kname}_960x540_1024c_256s_radius80.md",

@@ -382,8 +382,20 @@ int sp_step_kernel(const sp_handle* h);
 
 /* Which execution sp_step_local uses for this handle's shape on its device:
  * SP_KERNEL_PLAIN (three launches a frame) or SP_KERNEL_PERSISTENT_WAVE (one
- * persistent launch, a column group per wave); negative on a bad handle. */
+ * persistent launch, a column group per wave); negative on a bad handle.
+ * The persistent launch exchanges one frame at a time, or two frames at a
+ * time where the neighbourhood allows it (sp_step_local_kernel_for). */
 int sp_step_local_kernel(const sp_handle* h);
+
+/* Which execution sp_step_local uses for this handle with this grid width
+ * and radius: SP_KERNEL_PERSISTENT_PAIR (one persistent launch, two frames
+ * per exchange: every workgroup also decides the columns of its
+ * neighbourhoods' bounding box, at most 1024 of them, each over a window of
+ * at most 2048 columns), else as sp_step_local_kernel.  SP_EINVAL for
+ * grid_w outside 1..C, negative on a bad handle.  Informational: every
+ * execution gives the same results. */
+#define SP_KERNEL_PERSISTENT_PAIR 3
+int sp_step_local_kernel_for(const sp_handle* h, uint32_t grid_w, uint32_t radius);
 
 /* Which execution sp_step_boost uses for this handle's shape on its device:
  * SP_KERNEL_PLAIN (five launches a frame) or SP_KERNEL_PERSISTENT_WAVE (one

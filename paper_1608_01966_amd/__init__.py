@@ -29,6 +29,7 @@ __all__ = [
     "sp_step_plain", "sp_infer", "sp_step_many", "sp_step_many_raw", "sp_set_histogram", "sp_encode",
     "sp_inhibit_local", "sp_step_local", "sp_step_local_adaptive", "sp_step_boost", "sp_boost_state", "sp_boost_reset",
     "sp_encoded_bits", "sp_step_is_persistent", "sp_step_kernel", "sp_step_local_kernel",
+    "sp_step_local_kernel_for", "LOCAL_KERNELS",
     "sp_step_boost_kernel", "sp_test_stall", "STEP_KERNELS", "sp_state_bytes", "sp_get_state",
     "sp_set_state", "sp_get_boost_state", "sp_set_boost_state",
     "sp_sync",
@@ -340,6 +341,18 @@ def sp_step_local_kernel(h: int) -> str:
     return "k_sp_persistent_local" if code == 2 else "plain"
 
 
+# sp_step_local_kernel_for codes, and the HIP kernel each one runs.
+LOCAL_KERNELS = {0: "plain", 2: "k_sp_persistent_local", 3: "k_sp_persistent_local2"}
+
+
+def sp_step_local_kernel_for(h: int, grid_w: int, radius: int) -> str:
+    """The execution sp_step_local uses with this grid width and radius: a
+    LOCAL_KERNELS value."""
+    code = _check(lib().sp_step_local_kernel_for(ctypes.c_void_p(h), int(grid_w), int(radius)),
+                  "sp_step_local_kernel_for")
+    return LOCAL_KERNELS[code]
+
+
 def sp_step_boost_kernel(h: int) -> str:
     """The execution sp_step_boost uses: "plain" or "k_sp_persistent_boost"."""
     code = _check(lib().sp_step_boost_kernel(ctypes.c_void_p(h)), "sp_step_boost_kernel")
@@ -467,6 +480,10 @@ class SpatialPooler:
     def local_kernel(self) -> str:
         """The execution sp_step_local uses."""
         return sp_step_local_kernel(self.handle)
+
+    def local_kernel_for(self, grid_w: int, radius: int) -> str:
+        """The execution sp_step_local uses with this grid width and radius."""
+        return sp_step_local_kernel_for(self.handle, grid_w, radius)
 
     @property
     def boost_kernel(self) -> str:

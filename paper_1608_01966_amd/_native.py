@@ -86,6 +86,7 @@ SIGNATURES = [
     ("sp_step_is_persistent", ctypes.c_int, [P]),
     ("sp_step_kernel", ctypes.c_int, [P]),
     ("sp_step_local_kernel", ctypes.c_int, [P]),
+    ("sp_step_local_kernel_for", ctypes.c_int, [P, U32, U32]),
     ("sp_step_boost_kernel", ctypes.c_int, [P]),
     ("sp_test_stall", ctypes.c_int, [P, ctypes.c_uint32]),
     ("sp_state_bytes", ctypes.c_size_t, [CFG]),

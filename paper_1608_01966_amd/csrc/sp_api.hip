@@ -46,6 +46,12 @@ struct sp_handle {
   // grid, its exchange and the count of exchanges it has used
   const void* lkernel;
   uint32_t lgrid;
+  // the two-frames-per-exchange local instance (null: none), its columns per
+  // workgroup, its exchange region and the count of exchanges it has used
+  const void* lkernel2;
+  uint32_t lwgc;
+  uint64_t* xloc2;
+  uint64_t xloc2_pairs;
   const void* bkernel;  // persistent boosted step (null: per-frame launches)
   uint32_t bgrid;
   // sp_test_stall: the next persistent launch waits for entries that are
@@ -110,7 +116,7 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Workspace layout, each part 256-byte aligned.
 struct WsLayout {
-  size_t xchg, err, check, racc, ov, many_ovx, many_dec, xloc, total;
+  size_t xchg, err, check, racc, ov, many_ovx, many_dec, xloc, xloc2, total;
 };
 
 WsLayout ws_layout(const sp_config& c) {
@@ -127,7 +133,8 @@ WsLayout ws_layout(const sp_config& c) {
   // read in pairs of entries by 256-column words
   l.many_dec = align_up(l.many_ovx + sizeof(uint32_t) * align_up(c.num_columns, 256), 256);
   l.xloc = align_up(l.many_dec + sizeof(uint64_t), 256);
-  l.total = align_up(l.xloc + htmsp::persistent_local_exchange_bytes(c.num_columns), 256);
+  l.xloc2 = align_up(l.xloc + htmsp::persistent_local_exchange_bytes(c.num_columns), 256);
+  l.total = align_up(l.xloc2 + htmsp::persistent_local2_exchange_bytes(c.num_columns), 256);
   return l;
 }
 
@@ -249,6 +256,7 @@ uint32_t next_pow2(uint32_t x) {
 void plan_persistent(sp_handle* h) {
   h->persistent = false;
   h->lkernel = nullptr;
+  h->lkernel2 = nullptr;
   h->bkernel = nullptr;
   int dev = h->device, cus = 0, coop = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return;
@@ -284,6 +292,11 @@ void plan_persistent(sp_handle* h) {
     if (fits(kl)) {
       h->lkernel = kl;
       h->lgrid = wgrid;
+      const void* kl2 = htmsp::persistent_local2_kernel(rpc, nv, rw);
+      if (fits(kl2)) {
+        h->lkernel2 = kl2;
+        h->lwgc = htmsp::kPersistWaves * (rw / rpc);
+      }
     }
   }
   // The global step.
@@ -617,6 +630,7 @@ int sp_create(const sp_config* cfg, uint32_t* idx_dev, float* perm_dev, void* st
   h->many_ovx = reinterpret_cast<uint32_t*>(base + l.many_ovx);
   h->many_dec = reinterpret_cast<uint64_t*>(base + l.many_dec);
   h->xloc = reinterpret_cast<uint64_t*>(base + l.xloc);
+  h->xloc2 = reinterpret_cast<uint64_t*>(base + l.xloc2);
   // (run_check_state synchronises `s`, so the workspace is clear and idle
   // when it goes back to the pool on a failure)
   e = hipMemsetAsync(h->ws, 0, h->ws_bytes, s);
@@ -1070,6 +1084,7 @@ int sp_step_local(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames,
   hipStream_t s = static_cast<hipStream_t>(stream);
   IdleOnExit idle{h, s};
   note_learned(h, num_frames, learn);
+  const bool pair = h->lkernel2 && htmsp::persistent_local2_fits(sh.C, h->lwgc, grid_w, radius);
   if (h->lkernel) {
     htmsp::LocalArgs a;
     a.idx = h->idx;
@@ -1077,11 +1092,11 @@ int sp_step_local(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames,
     a.frames = frames_dev;
     a.ov_out = overlaps_dev;
     a.active_out = active_dev;
-    a.xchg = h->xloc;
+    a.xchg = pair ? h->xloc2 : h->xloc;
     a.err = h->err;
     a.F = num_frames;
     a.learn = learn ? 1u : 0u;
-    a.frame_base = (uint32_t)h->xloc_frames;
+    a.frame_base = (uint32_t)(pair ? h->xloc2_pairs : h->xloc_frames);
     a.replicas = htmsp::kPersistReplicas;
     a.spin_limit = h->stall_spins ? h->stall_spins : kSpinLimit;
     a.stall = h->stall_spins ? 1u : 0u;
@@ -1090,10 +1105,13 @@ int sp_step_local(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames,
     a.radius = radius;
     a.sh = sh;
     void* args[] = {&a};
-    hipError_t e = hipLaunchCooperativeKernel(h->lkernel, dim3(h->lgrid),
+    hipError_t e = hipLaunchCooperativeKernel(pair ? h->lkernel2 : h->lkernel, dim3(h->lgrid),
                                               dim3(htmsp::kPersistWaves * 64), args, 0, s);
     if (e != hipSuccess) return hip_fail(e, "persistent local step launch");
-    h->xloc_frames += num_frames;
+    if (pair)
+      h->xloc2_pairs += (num_frames + 1) / 2;
+    else
+      h->xloc_frames += num_frames;
     return add_histogram_active(h, active_dev, num_frames, s);
   }
   for (uint32_t t = 0; t < num_frames; ++t) {
@@ -1333,6 +1351,14 @@ int sp_step_boost_kernel(const sp_handle* h) {
 
 int sp_step_local_kernel(const sp_handle* h) {
   if (!h) return fail(SP_EINVAL, "handle is NULL");
+  return h->lkernel ? SP_KERNEL_PERSISTENT_WAVE : SP_KERNEL_PLAIN;
+}
+
+int sp_step_local_kernel_for(const sp_handle* h, uint32_t grid_w, uint32_t radius) {
+  if (!h) return fail(SP_EINVAL, "handle is NULL");
+  if (grid_w < 1 || grid_w > h->sh.C) return fail(SP_EINVAL, "grid_w=%u outside 1..C", grid_w);
+  if (h->lkernel2 && htmsp::persistent_local2_fits(h->sh.C, h->lwgc, grid_w, radius))
+    return SP_KERNEL_PERSISTENT_PAIR;
   return h->lkernel ? SP_KERNEL_PERSISTENT_WAVE : SP_KERNEL_PLAIN;
 }
 

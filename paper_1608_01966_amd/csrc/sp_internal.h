@@ -70,6 +70,16 @@ struct LocalArgs {
 const void* persistent_local_kernel(uint32_t rpc, uint32_t nv, uint32_t rw);
 // Exchange bytes of the persistent local step for C columns.
 size_t persistent_local_exchange_bytes(uint32_t C);
+// The two-frames-per-exchange local instance (same shapes), its exchange
+// bytes (three arrays), and whether it serves a neighbourhood: every
+// workgroup of `wgc` columns decides a halo of at most kLocal2MaxHalo
+// columns per pair, one thread each, each scanning at most kLocal2MaxWindow
+// neighbours.
+constexpr uint64_t kLocal2MaxHalo = 1024;
+constexpr uint64_t kLocal2MaxWindow = 2048;
+const void* persistent_local2_kernel(uint32_t rpc, uint32_t nv, uint32_t rw);
+size_t persistent_local2_exchange_bytes(uint32_t C);
+bool persistent_local2_fits(uint32_t C, uint32_t wgc, uint32_t grid_w, uint32_t radius);
 
 // Waves per workgroup of the one-column-group-per-wave kernel.
 constexpr uint32_t kPersistWaves = 4;

@@ -365,6 +365,408 @@ __global__ __launch_bounds__(kPersistWaves * kWave) void k_sp_persistent_local(L
   }
 }
 
+// Algorithm 2 for column d = (dx, dy) with overlap v in one thread, against
+// one frame's copy of every column's overlap (word i holds columns 4i..4i+3
+// as 16-bit fields, tag bits cleared): active iff v >= 2 and fewer than n
+// other columns of its neighbourhood have an overlap >= v.  Counts four
+// columns a word with the field compare of the top-k: the end words of each
+// window row under a mask, the words between in runs of eight loads (the
+// last run's loads past the row read zero words, which count nothing); d
+// itself (overlap v) is counted once, so the count stops at n + 1.
+__device__ __forceinline__ bool local_active(uint32_t dx, uint32_t dy, uint32_t v,
+                                             const uint64_t* w64, uint32_t C, uint32_t grid_w,
+                                             uint32_t rows, uint32_t radius, uint32_t n) {
+  if (v < 2) return false;
+  const uint32_t y0 = dy >= radius ? dy - radius : 0u, y1 = min(dy + radius, rows - 1);
+  const uint32_t x0 = dx >= radius ? dx - radius : 0u, x1 = min(dx + radius, grid_w - 1);
+  const uint32_t add = 0x8000u - v, lim = n + 1;
+  auto cnt = [&](uint64_t w) { return (uint32_t)__popcll(field_add(w, add) & kHighBits); };
+  uint32_t k = 0;
+  for (uint32_t y = y0; y <= y1; ++y) {
+    const uint32_t lo = y * grid_w + x0;
+    if (lo >= C) break;  // the ragged last row ends before this segment
+    const uint32_t hi = min(y * grid_w + x1, C - 1);
+    const uint32_t i0 = lo >> 2, i1 = hi >> 2;
+    const uint64_t m0 = kHighBits & (~0ull << (16 * (lo & 3u)));
+    const uint64_t m1 = kHighBits & (~0ull >> (16 * (3u - (hi & 3u))));
+    if (i0 == i1) {
+      k += (uint32_t)__popcll(field_add(w64[i0], add) & m0 & m1);
+    } else {
+      k += (uint32_t)__popcll(field_add(w64[i0], add) & m0) +
+           (uint32_t)__popcll(field_add(w64[i1], add) & m1);
+      uint32_t i = i0 + 1;
+      for (; i + 8 <= i1 && k < lim; i += 8) {
+        uint64_t wv[8];
+#pragma unroll
+        for (uint32_t u = 0; u < 8; ++u) wv[u] = w64[i + u];
+#pragma unroll
+        for (uint32_t u = 0; u < 8; ++u) k += cnt(wv[u]);
+      }
+      if (i < i1 && k < lim) {
+        uint64_t wv[8];
+#pragma unroll
+        for (uint32_t u = 0; u < 8; ++u) {
+          const uint64_t x = w64[min(i + u, i1)];
+          wv[u] = i + u < i1 ? x : 0ull;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < 8; ++u) k += cnt(wv[u]);
+      }
+    }
+    if (k >= lim) return false;
+  }
+  return true;
+}
+
+// Persistent learning step with local inhibition, two frames per exchange
+// (the lookahead of the global step's k_sp_persistent_w): learning couples
+// frame t + 1 to frame t only through each column's own synapses, so every
+// wave publishes, with its columns' frame-t overlaps, their frame-(t+1)
+// overlaps if they stay inactive in frame t and if they are active.  A
+// workgroup then decides frame t for every column of its halo -- the
+// bounding box of its columns' neighbourhoods, one column per thread,
+// local_active on the frame-t copy -- and writes each halo column's
+// frame-(t+1) overlap, picked by that decision, into LDS; each wave decides
+// its own columns' frame t + 1 from there (lanes across a window row, as
+// the one-frame kernel does), learns on the columns active in either frame,
+// and computes the next pair's overlaps (speculatively while the exchange
+// is in flight, redone for the columns that learned).  The results are
+// exactly those of stepping the frames one by one.  Exchange layout, tags,
+// poller, publishers and abort are those of the global two-frame kernel, in
+// the local pair region of the workspace with its own exchange counter.
+template <int RPC, int NV, int RW>
+__global__ __launch_bounds__(kPersistWaves * kWave) void k_sp_persistent_local2(LocalArgs a) {
+  constexpr uint32_t CPW = RW / RPC;
+  constexpr uint32_t CPAD = NV * 4 * kWave;      // entries per exchange array
+  constexpr uint32_t NARR = 3;                   // frame t, frame t+1 if inactive, if active
+  constexpr uint32_t WGC = kPersistWaves * CPW;  // columns per workgroup
+  constexpr uint32_t kSeenAbort = 0xFFFFFFFFu;
+  static_assert(kPersistWaves == NARR + 1, "waves 1..3 publish the three arrays");
+  __shared__ uint64_t xl[2][NARR][NV * kWave];  // the exchange, word i = columns 4i..4i+3
+  __shared__ uint64_t e1w[NV * kWave];          // frame t+1 overlaps of the halo columns
+  __shared__ uint8_t a0[CPAD];                  // frame-t decisions of the halo columns
+  __shared__ uint32_t hcell[kLocal2MaxHalo];    // halo cells: x | y << 16 (y * grid_w + x < C)
+  __shared__ uint32_t nhalo;
+  __shared__ uint32_t pub[NARR][WGC];
+  __shared__ uint32_t seen;
+  const Shape sh = a.sh;
+  const uint32_t lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  const uint32_t gw = blockIdx.x * kPersistWaves + wave;
+  const uint32_t c_begin = gw * CPW;
+  const uint32_t wg_begin = blockIdx.x * WGC;
+  const uint32_t ncols = c_begin < sh.C ? min(CPW, sh.C - c_begin) : 0u;
+  const uint32_t rows = (sh.C + a.grid_w - 1) / a.grid_w;
+  const bool mine = lane < ncols;
+  if (threadIdx.x == 0) seen = 0;
+
+  // The halo box (rows hy0..hy0+bh-1, grid columns hx0..hx0+bw-1): the
+  // neighbourhoods of the workgroup's columns; empty past C.
+  // The halo box's cells that are columns (< C), listed once in LDS.
+  if (threadIdx.x == 0) nhalo = 0;
+  __syncthreads();
+  if (wg_begin < sh.C) {
+    const uint32_t wg_last = min(wg_begin + WGC, sh.C) - 1;
+    const uint32_t yf = wg_begin / a.grid_w, yl = wg_last / a.grid_w;
+    const uint32_t xf = yf == yl ? wg_begin % a.grid_w : 0u;
+    const uint32_t xl_ = yf == yl ? wg_last % a.grid_w : a.grid_w - 1;
+    const uint32_t hy0 = yf >= a.radius ? yf - a.radius : 0u;
+    const uint32_t hx0 = xf >= a.radius ? xf - a.radius : 0u;
+    const uint32_t bh = min(yl + a.radius, rows - 1) - hy0 + 1;
+    const uint32_t bw = min(xl_ + a.radius, a.grid_w - 1) - hx0 + 1;
+    for (uint32_t i = threadIdx.x; i < bh * bw; i += kPersistWaves * kWave) {
+      const uint32_t y = hy0 + i / bw, x = hx0 + i % bw;
+      if (y * a.grid_w + x < sh.C) hcell[atomicAdd(&nhalo, 1u)] = x | (y << 16);
+    }
+  }
+
+  uint32_t st[RW], msk[RW], wi[RW];
+  uint32_t row_ok = 0;
+#pragma unroll
+  for (uint32_t r = 0; r < RW; ++r) {
+    const uint32_t j = r / RPC, s = (r % RPC) * kWave + lane;
+    const bool ok = j < ncols && s < sh.S;
+    const size_t off = ok ? (size_t)(c_begin + j) * sh.S + s : 0;
+    const uint32_t i = min(a.idx[off], sh.N - 1);
+    const uint32_t q = perm_to_q(a.perm[off]);
+    st[r] = ok ? (i << 9) | q : 0u;
+    msk[r] = (ok && q >= sh.theta) ? (1u << (i & 31u)) : 0u;
+    wi[r] = ok ? i >> 5 : 0u;
+    row_ok |= ok ? 1u << r : 0u;
+  }
+  const uint32_t rep = xcc_id() % a.replicas;
+  bool abort = false;
+
+  auto stage = [&](const uint32_t(&o0)[CPW], const uint32_t(&oL)[CPW], const uint32_t(&oW)[CPW]) {
+    if (lane < CPW) {
+      pub[0][wave * CPW + lane] = lane_value(o0, lane);
+      pub[1][wave * CPW + lane] = lane_value(oL, lane);
+      pub[2][wave * CPW + lane] = lane_value(oW, lane);
+    }
+  };
+  // Input words of frames t and t + 1 (clamped to the last frame).
+  auto gather = [&](uint32_t t, uint32_t (&x0)[RW], uint32_t (&x1)[RW]) {
+    const uint32_t* f0 = a.frames + (size_t)min(t, a.F - 1) * sh.W;
+    const uint32_t* f1 = a.frames + (size_t)min(t + 1, a.F - 1) * sh.W;
+#pragma unroll
+    for (uint32_t r = 0; r < RW; ++r) {
+      x0[r] = f0[wi[r]];
+      x1[r] = f1[wi[r]];
+    }
+  };
+  // Frame t's overlap, the state after learning frame t, and frame t + 1's
+  // overlap with the current state and with that state.
+  auto products = [&](uint32_t cols, const uint32_t (&x0)[RW], const uint32_t (&x1)[RW],
+                      uint32_t (&o0)[CPW], uint32_t (&oL)[CPW], uint32_t (&oW)[CPW],
+                      uint32_t (&sW)[RW], uint32_t (&mW)[RW]) {
+#pragma unroll
+    for (uint32_t j = 0; j < CPW; ++j) {
+      if ((cols >> j) & 1u) {
+        uint32_t c0 = 0, cL = 0, cW = 0;
+#pragma unroll
+        for (uint32_t rr = 0; rr < RPC; ++rr) {
+          const uint32_t r = j * RPC + rr;
+          const uint32_t i = st[r] >> 9;
+          const uint32_t q = learn_q(st[r] & 511u, input_bit(x0[r], i), sh);
+          const bool ok = a.learn && ((row_ok >> r) & 1u);
+          sW[r] = ok ? (i << 9) | q : st[r];
+          mW[r] = ok ? (q >= sh.theta ? 1u << (i & 31u) : 0u) : msk[r];
+          c0 += (uint32_t)__popcll(__ballot((x0[r] & msk[r]) != 0u));
+          cL += (uint32_t)__popcll(__ballot((x1[r] & msk[r]) != 0u));
+          cW += (uint32_t)__popcll(__ballot((x1[r] & mW[r]) != 0u));
+        }
+        const bool live = j < ncols;
+        o0[j] = (live && c0 >= sh.m) ? c0 : 0u;
+        oL[j] = (live && cL >= sh.m) ? cL : 0u;
+        oW[j] = (live && cW >= sh.m) ? cW : 0u;
+      }
+    }
+  };
+  // Algorithm 2 for own column c with overlap v against a copy by column
+  // (lanes split each row of the window, four 64-column chunks a step, all
+  // four reads in flight; stops at n).
+  auto decide = [&](uint32_t c, uint32_t v, const uint16_t* ov) {
+    if (v < 2) return false;
+    const uint32_t cx = c % a.grid_w, cy = c / a.grid_w;
+    const uint32_t y0 = cy >= a.radius ? cy - a.radius : 0u;
+    const uint32_t y1 = min(cy + a.radius, rows - 1);
+    const uint32_t x0 = cx >= a.radius ? cx - a.radius : 0u;
+    const uint32_t x1 = min(cx + a.radius, a.grid_w - 1);
+    uint32_t k = 0;
+    for (uint32_t y = y0; y <= y1 && k < sh.k; ++y) {
+      for (uint32_t xb = x0; xb <= x1 && k < sh.k; xb += 4 * kWave) {
+        uint32_t o[4];
+        bool in[4];
+#pragma unroll
+        for (uint32_t u = 0; u < 4; ++u) {
+          const uint32_t x = xb + u * kWave + lane, d = y * a.grid_w + x;
+          in[u] = x <= x1 && d < sh.C && d != c;
+          o[u] = ov[in[u] ? d : c];
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < 4; ++u)
+          k += (uint32_t)__popcll(__ballot(in[u] && (o[u] & 0x3FFFu) >= v));
+      }
+    }
+    return k < sh.k;
+  };
+
+  constexpr uint32_t kAllCols = (1u << CPW) - 1u;
+  uint64_t* x64w = a.xchg;
+  auto run = [&](auto role) {
+    constexpr bool POLL = decltype(role)::value;
+    uint32_t w0[RW], w1[RW];  // this pair's input words
+    uint32_t ov0[CPW], ovL[CPW], ovW[CPW];
+    uint32_t stW[RW], mskW[RW];
+    gather(0, w0, w1);
+    products(kAllCols, w0, w1, ov0, ovL, ovW, stW, mskW);
+    stage(ov0, ovL, ovW);
+    __syncthreads();
+    for (uint32_t t = 0; t < a.F; t += 2) {
+      const bool two = t + 1 < a.F;
+      const uint32_t pair = t / 2;
+      const uint32_t g = a.frame_base + pair;
+      const uint32_t slot = g & 1u;
+      const uint32_t tg = ((g + 1u) & 3u) << kTagShift;
+      const uint64_t* xs = x64w + (size_t)(rep * 2 + slot) * NARR * (CPAD / 4);
+      if constexpr (!POLL) {
+        const uint32_t arr = wave - 1;
+        if (lane < WGC / 4) {
+          const uint64_t word = (uint64_t)(tg | pub[arr][4 * lane]) |
+                                ((uint64_t)(tg | pub[arr][4 * lane + 1]) << 16) |
+                                ((uint64_t)(tg | pub[arr][4 * lane + 2]) << 32) |
+                                ((uint64_t)(tg | pub[arr][4 * lane + 3]) << 48);
+          for (uint32_t rr = 0; rr < a.replicas; ++rr)
+            store_word(x64w + (((size_t)(rr * 2 + slot) * NARR + arr) * CPAD + wg_begin) / 4 + lane,
+                       word);
+        }
+      }
+      const uint32_t tn = t + 2;
+      const bool has_next = tn < a.F;
+      uint32_t n0[RW], n1[RW];
+      gather(tn, n0, n1);
+      uint32_t sov0[CPW], sovL[CPW], sovW[CPW];
+      uint32_t sstW[RW], smskW[RW];
+      if (has_next) products(kAllCols, n0, n1, sov0, sovL, sovW, sstW, smskW);
+
+      if constexpr (POLL) {
+        uint64_t v0[NV], vL[NV], vW[NV];
+#pragma unroll
+        for (int u = 0; u < NV; ++u) {
+          v0[u] = load_entries(xs + u * kWave + lane);
+          vL[u] = load_entries(xs + CPAD / 4 + u * kWave + lane);
+          vW[u] = load_entries(xs + 2 * (CPAD / 4) + u * kWave + lane);
+        }
+        // (a.stall != 0 only in tests of the failure path)
+        const uint64_t tagw = (uint64_t)((((g + 1u + a.stall) & 3u) << kTagShift)) * kOnes16;
+        uint32_t spins = 0;
+        while (true) {
+          bool ok = true;
+#pragma unroll
+          for (int u = 0; u < NV; ++u) {
+            const uint64_t tm = tag_mask(u, lane, sh.C);
+            ok = ok && ((v0[u] ^ tagw) & tm) == 0ull && ((vL[u] ^ tagw) & tm) == 0ull &&
+                 ((vW[u] ^ tagw) & tm) == 0ull;
+          }
+          if (__all(ok)) break;
+          if (++spins > a.spin_limit || ((spins & 63u) == 0 && load_tagged(a.err) != 0)) {
+            abort = true;
+            break;
+          }
+#pragma unroll
+          for (int u = 0; u < NV; ++u) {
+            const uint64_t tm = tag_mask(u, lane, sh.C);
+            if (((v0[u] ^ tagw) & tm) != 0ull) v0[u] = load_entries(xs + u * kWave + lane);
+            if (((vL[u] ^ tagw) & tm) != 0ull) vL[u] = load_entries(xs + CPAD / 4 + u * kWave + lane);
+            if (((vW[u] ^ tagw) & tm) != 0ull)
+              vW[u] = load_entries(xs + 2 * (CPAD / 4) + u * kWave + lane);
+          }
+        }
+        if (abort) {
+          lds_release(&seen, kSeenAbort);
+          break;
+        }
+        // (tags cleared: the halo pass compares whole words)
+#pragma unroll
+        for (int u = 0; u < NV; ++u) {
+          xl[pair & 1][0][u * kWave + lane] = v0[u] & kFieldBits;
+          xl[pair & 1][1][u * kWave + lane] = vL[u] & kFieldBits;
+          xl[pair & 1][2][u * kWave + lane] = vW[u] & kFieldBits;
+        }
+        lds_release(&seen, pair + 1);
+      } else {
+        // Bounded by wave 0, which sets `seen` within its own spin limit.
+        uint32_t sv;
+        while ((sv = lds_acquire(&seen)) <= pair) __builtin_amdgcn_s_sleep(0);
+        if (sv == kSeenAbort) {
+          abort = true;
+          break;
+        }
+      }
+
+      // Frame t for every halo column, and its frame-(t+1) overlap.
+      const uint64_t* x0w = xl[pair & 1][0];
+      const uint16_t* xL16 = reinterpret_cast<const uint16_t*>(xl[pair & 1][1]);
+      const uint16_t* xW16 = reinterpret_cast<const uint16_t*>(xl[pair & 1][2]);
+      const uint16_t* x016 = reinterpret_cast<const uint16_t*>(x0w);
+      uint16_t* e1 = reinterpret_cast<uint16_t*>(e1w);
+      for (uint32_t i = threadIdx.x; i < nhalo; i += kPersistWaves * kWave) {
+        const uint32_t xy = hcell[i], dx = xy & 0xFFFFu, dy = xy >> 16;
+        const uint32_t d = dy * a.grid_w + dx;
+        const bool act =
+            local_active(dx, dy, x016[d], x0w, sh.C, a.grid_w, rows, a.radius, sh.k);
+        a0[d] = act ? 1u : 0u;
+        e1[d] = act ? xW16[d] : xL16[d];
+      }
+      __syncthreads();
+
+      // Own columns: frame t from the halo pass, frame t + 1 against it.
+      uint32_t sel0 = 0, sel1 = 0;
+#pragma unroll
+      for (uint32_t j = 0; j < CPW; ++j)
+        if (j < ncols && a0[c_begin + j]) sel0 |= 1u << j;
+      uint32_t my1[CPW];
+#pragma unroll
+      for (uint32_t j = 0; j < CPW; ++j) my1[j] = ((sel0 >> j) & 1u) ? ovW[j] : ovL[j];
+      if (two) {
+#pragma unroll
+        for (uint32_t j = 0; j < CPW; ++j)
+          if (j < ncols && decide(c_begin + j, my1[j], e1)) sel1 |= 1u << j;
+      }
+      if (mine) {
+        const size_t o = (size_t)t * sh.C + c_begin + lane;
+        a.active_out[o] = (uint8_t)((sel0 >> lane) & 1u);
+        if (a.ov_out) a.ov_out[o] = (int32_t)lane_value(ov0, lane);
+        if (two) {
+          a.active_out[o + sh.C] = (uint8_t)((sel1 >> lane) & 1u);
+          if (a.ov_out) a.ov_out[o + sh.C] = (int32_t)lane_value(my1, lane);
+        }
+      }
+
+      // Learning on the own columns active in frame t (its state), then t + 1.
+      uint32_t changed = 0;
+      if (a.learn) {
+        changed = sel0 | sel1;
+#pragma unroll
+        for (uint32_t j = 0; j < CPW; ++j) {
+          if ((changed >> j) & 1u) {
+#pragma unroll
+            for (uint32_t rr = 0; rr < RPC; ++rr) {
+              const uint32_t r = j * RPC + rr;
+              if ((sel0 >> j) & 1u) {
+                st[r] = stW[r];
+                msk[r] = mskW[r];
+              }
+              if ((sel1 >> j) & 1u) {
+                const uint32_t i = st[r] >> 9;
+                const uint32_t q = learn_q(st[r] & 511u, input_bit(w1[r], i), sh);
+                const bool ok = (row_ok >> r) & 1u;
+                st[r] = ok ? (i << 9) | q : st[r];
+                msk[r] = ok ? (q >= sh.theta ? 1u << (i & 31u) : 0u) : msk[r];
+              }
+            }
+          }
+        }
+      }
+
+      if (has_next) {
+        if (changed) products(changed, n0, n1, sov0, sovL, sovW, sstW, smskW);
+#pragma unroll
+        for (uint32_t r = 0; r < RW; ++r) {
+          w0[r] = n0[r];
+          w1[r] = n1[r];
+          stW[r] = sstW[r];
+          mskW[r] = smskW[r];
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < CPW; ++j) {
+          ov0[j] = sov0[j];
+          ovL[j] = sovL[j];
+          ovW[j] = sovW[j];
+        }
+        stage(ov0, ovL, ovW);
+      }
+      __syncthreads();
+    }
+  };
+  if (a.F > 0) {
+    if (wave == 0)
+      run(LocalRole<true>{});
+    else
+      run(LocalRole<false>{});
+  }
+  if (abort) {
+    if (wave == 0 && lane == 0) store_tagged(a.err, 1u);
+    return;
+  }
+  if (a.learn) {
+#pragma unroll
+    for (uint32_t r = 0; r < RW; ++r) {
+      const uint32_t j = r / RPC, s = (r % RPC) * kWave + lane;
+      if ((row_ok >> r) & 1u) a.perm[(size_t)(c_begin + j) * sh.S + s] = q_to_perm(st[r] & 511u);
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t launch_inhibit_local(const int32_t* ov, uint32_t F, uint32_t C, uint32_t grid_w,
@@ -424,6 +826,42 @@ const void* persistent_local_kernel(uint32_t rpc, uint32_t nv, uint32_t rw) {
 
 size_t persistent_local_exchange_bytes(uint32_t C) {
   return (size_t)2 * kPersistMaxReplicas * persistent_exchange_entries(C) * sizeof(uint16_t);
+}
+
+const void* persistent_local2_kernel(uint32_t rpc, uint32_t nv, uint32_t rw) {
+#define HTMSP_PL2(P, V, R)                             \
+  if (rpc == P && nv == V && rw == R)                  \
+    return reinterpret_cast<const void*>(&k_sp_persistent_local2<P, V, R>);
+  HTMSP_PL2(1, 1, 4) HTMSP_PL2(1, 2, 4) HTMSP_PL2(1, 4, 4) HTMSP_PL2(1, 8, 4) HTMSP_PL2(1, 16, 8)
+  HTMSP_PL2(2, 1, 4) HTMSP_PL2(2, 2, 4) HTMSP_PL2(2, 4, 4) HTMSP_PL2(2, 8, 8) HTMSP_PL2(2, 16, 16)
+  HTMSP_PL2(4, 1, 4) HTMSP_PL2(4, 2, 4) HTMSP_PL2(4, 4, 8) HTMSP_PL2(4, 8, 16) HTMSP_PL2(4, 16, 16)
+  HTMSP_PL2(8, 1, 8) HTMSP_PL2(8, 2, 8) HTMSP_PL2(8, 4, 16) HTMSP_PL2(8, 8, 16) HTMSP_PL2(16, 1, 16)
+  HTMSP_PL2(16, 2, 16) HTMSP_PL2(16, 4, 16)
+#undef HTMSP_PL2
+  return nullptr;
+}
+
+size_t persistent_local2_exchange_bytes(uint32_t C) {
+  return (size_t)2 * kPersistReplicas * 3 * persistent_exchange_entries(C) * sizeof(uint16_t);
+}
+
+bool persistent_local2_fits(uint32_t C, uint32_t wgc, uint32_t grid_w, uint32_t radius) {
+  if (grid_w < 1 || grid_w > C || wgc < 1) return false;
+  const uint64_t rows = (C + grid_w - 1) / grid_w;
+  const uint64_t win = std::min<uint64_t>(rows, 2ull * radius + 1) *
+                       std::min<uint64_t>(grid_w, 2ull * radius + 1);
+  if (win > kLocal2MaxWindow) return false;
+  // every workgroup's halo box, as the kernel computes it
+  for (uint64_t b = 0; b * wgc < C; ++b) {
+    const uint64_t first = b * wgc, last = std::min<uint64_t>(first + wgc, C) - 1;
+    const uint64_t yf = first / grid_w, yl = last / grid_w;
+    const uint64_t xf = yf == yl ? first % grid_w : 0, xl = yf == yl ? last % grid_w : grid_w - 1;
+    const uint64_t y0 = yf >= radius ? yf - radius : 0, x0 = xf >= radius ? xf - radius : 0;
+    const uint64_t bh = std::min<uint64_t>(yl + radius, rows - 1) - y0 + 1;
+    const uint64_t bw = std::min<uint64_t>(xl + radius, grid_w - 1) - x0 + 1;
+    if (bh * bw > kLocal2MaxHalo) return false;
+  }
+  return true;
 }
 
 }  // namespace htmsp

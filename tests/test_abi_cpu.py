@@ -76,6 +76,8 @@ def test_null_handle_and_args_are_rejected_on_host():
     assert L.sp_step_plain(None, None, 0, 1, None, None, None) == sp.SP_EINVAL
     assert L.sp_sync(None, None) == sp.SP_EINVAL
     assert L.sp_step_is_persistent(None) == sp.SP_EINVAL
+    assert L.sp_step_local_kernel(None) == sp.SP_EINVAL
+    assert L.sp_step_local_kernel_for(None, 1024, 80) == sp.SP_EINVAL
     assert L.sp_destroy(None) == sp.SP_OK
     out = ctypes.c_void_p()
     cfg = _native.SpConfig.from_dict(synth.sp_config(100, 4, 8, 1, 2))

@@ -21,21 +21,34 @@ def _step(kind, pool, cfg, frames, F):
         sp.sp_step(pool.handle, cfg, frames, True, None,
                    torch.empty((F, k), dtype=torch.int32, device="cuda"))
     elif kind == "local":
+        # two frames per exchange
         sp.sp_step_local(pool.handle, cfg, frames, True, 1024, 80, None,
+                         torch.empty((F, C), dtype=torch.uint8, device="cuda"))
+    elif kind == "local_one_frame":
+        # a 64 x 64 grid whose radius-40 windows are too large for two frames
+        # per exchange
+        sp.sp_step_local(pool.handle, cfg, frames, True, 64, 40, None,
                          torch.empty((F, C), dtype=torch.uint8, device="cuda"))
     else:
         sp.sp_step_boost(pool.handle, cfg, BC, frames, True, None,
                          torch.empty((F, k), dtype=torch.int32, device="cuda"))
 
 
-@pytest.mark.parametrize("kind", ["global", "local", "boost"])
+@pytest.mark.parametrize("kind", ["global", "local", "local_one_frame", "boost"])
 def test_stalled_exchange_drains_and_reports(kind):
     import torch
-    w = synth.workload_paper_scale(frames=8, columns=1024, synapses=256)
+    if kind == "local_one_frame":
+        w = synth.workload_paper_scale(frames=8, columns=4096, synapses=64)
+    else:
+        w = synth.workload_paper_scale(frames=8, columns=1024, synapses=256)
     cfg = w.cfg
     pool = sp.SpatialPooler(cfg, w.idx, w.perm)
-    assert {"global": pool.kernel, "local": pool.local_kernel,
-            "boost": pool.boost_kernel}[kind] != "plain"
+    assert {"global": pool.kernel, "local": pool.local_kernel_for(1024, 80),
+            "local_one_frame": pool.local_kernel_for(64, 40),
+            "boost": pool.boost_kernel}[kind] == {
+                "global": "k_sp_persistent_w", "local": "k_sp_persistent_local2",
+                "local_one_frame": "k_sp_persistent_local",
+                "boost": "k_sp_persistent_boost"}[kind]
     frames = torch.from_numpy(w.frames.view(np.int32)).cuda()
     sp.sp_test_stall(pool.handle, 200)
     _step(kind, pool, cfg, frames, 8)

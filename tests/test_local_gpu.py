@@ -111,6 +111,61 @@ def test_step_local_shapes(shape):
     assert kern == ("plain" if C > 4096 or S > 1024 else "k_sp_persistent_local")
 
 
+def test_step_local_kernel_choice():
+    """Two frames per exchange wherever every workgroup's halo (the bounding
+    box of its columns' neighbourhoods) and every window are small enough;
+    one frame per exchange otherwise; per-frame launches past the persistent
+    shapes."""
+    w = synth.workload_paper_scale(frames=1, columns=1024, synapses=256)
+    pool = sp.SpatialPooler(w.cfg, w.idx, w.perm)
+    assert pool.local_kernel_for(1024, 80) == "k_sp_persistent_local2"
+    assert pool.local_kernel_for(32, 20) == "k_sp_persistent_local2"
+    pool.close()
+    w = synth.workload_paper_scale(frames=1, columns=4096, synapses=64)
+    pool = sp.SpatialPooler(w.cfg, w.idx, w.perm)
+    assert pool.local_kernel_for(64, 2) == "k_sp_persistent_local2"
+    assert pool.local_kernel_for(64, 40) == "k_sp_persistent_local"   # 4096-column windows
+    assert pool.local_kernel_for(4096, 1200) == "k_sp_persistent_local"  # 2401-column windows
+    with pytest.raises(sp.SpError):
+        pool.local_kernel_for(0, 2)
+    pool.close()
+    cfg = synth.sp_config(20000, 5000, 16, 1, 3)
+    w = synth.random_instance(3, cfg, frames=1, density=0.1)
+    pool = sp.SpatialPooler(cfg, w.idx, w.perm)
+    assert pool.local_kernel_for(100, 2) == "plain"
+    pool.close()
+
+
+def test_step_local_one_and_two_frame_exchanges_alternate():
+    """Calls on one handle switching between the two persistent kernels
+    (radius 2 and 40 on a 64 x 64 grid), with odd frame counts: each keeps
+    its own exchange region and sequence, and the state carries over."""
+    import torch
+    cfg = synth.sp_config(30000, 4096, 64, 3, 5)
+    w = synth.random_instance(77, cfg, frames=13, density=0.1)
+    pool = sp.SpatialPooler(cfg, w.idx, w.perm)
+    frames = torch.from_numpy(np.ascontiguousarray(w.frames).view(np.int32)).cuda()
+    C = cfg["num_columns"]
+    ov = torch.empty((13, C), dtype=torch.int32, device="cuda")
+    act = torch.empty((13, C), dtype=torch.uint8, device="cuda")
+    plan = [(0, 5, 2), (5, 8, 40), (8, 9, 2), (9, 12, 2), (12, 13, 40)]
+    kinds = set()
+    for a0, a1, r in plan:
+        kinds.add(pool.local_kernel_for(64, r))
+        sp.sp_step_local(pool.handle, cfg, frames[a0:a1], True, 64, r, ov[a0:a1], act[a0:a1])
+    pool.sync()
+    assert kinds == {"k_sp_persistent_local", "k_sp_persistent_local2"}
+    perm = w.perm
+    for a0, a1, r in plan:
+        e_ov, e_act, e_perm = oracle.run_local(cfg, w.idx, perm, w.frames[a0:a1], 64, r, 5)
+        assert np.array_equal(ov[a0:a1].cpu().numpy(), e_ov), (a0, a1, r)
+        assert np.array_equal(act[a0:a1].cpu().numpy(), e_act), (a0, a1, r)
+        perm = e_perm
+    assert np.array_equal(pool.perm.cpu().numpy().astype(np.float64), perm)
+    assert act.cpu().numpy().sum() > 0
+    pool.close()
+
+
 def test_step_local_learning_off_and_no_overlaps():
     w = synth.workload_paper_scale(frames=9, columns=1024, synapses=256)
     w.cfg["winners"] = 6

@@ -231,10 +231,29 @@ __global__ __launch_bounds__(kPersistWaves * kWave) void k_sp_persistent_boost(B
       }
     }
   };
-  // Bit (4u + q) of this lane's mask `m`, for column c of the frame order.
-  auto column_bit = [&](uint32_t m, uint32_t c) {
-    const uint32_t src = (c % (4 * kWave)) / 4;
-    return ((uint32_t)__shfl((int)m, (int)src) >> ((c / (4 * kWave)) * 4 + c % 4)) & 1u;
+  // Bits of the own columns (bit j: column c_begin + j) in the masks `m`
+  // whose bit 4u + q in lane l stands for column u * 256 + 4l + q.  A wave's
+  // CPW columns start at a multiple of CPW (<= 16), so up to four of them
+  // share one lane, whose mask is then read as a scalar.  Every lane calls it.
+  auto own_bits = [&](uint32_t m) {
+    uint32_t r = 0;
+    if constexpr (CPW <= 4) {
+      const uint32_t src = __builtin_amdgcn_readfirstlane((c_begin % (4 * kWave)) / 4);
+      const uint32_t ms = __builtin_amdgcn_readlane(m, src);
+#pragma unroll
+      for (uint32_t j = 0; j < CPW; ++j) {
+        const uint32_t c = c_begin + j;
+        r |= (j < ncols && ((ms >> ((c / (4 * kWave)) * 4 + c % 4)) & 1u)) ? 1u << j : 0u;
+      }
+    } else {
+#pragma unroll
+      for (uint32_t j = 0; j < CPW; ++j) {
+        const uint32_t c = c_begin + j;
+        const uint32_t ms = (uint32_t)__shfl((int)m, (int)((c % (4 * kWave)) / 4));
+        r |= (j < ncols && ((ms >> ((c / (4 * kWave)) * 4 + c % 4)) & 1u)) ? 1u << j : 0u;
+      }
+    }
+    return r;
   };
 
   auto run = [&](auto role) {
@@ -316,6 +335,8 @@ __global__ __launch_bounds__(kPersistWaves * kWave) void k_sp_persistent_boost(B
       const uint32_t nsel = T ? sh.k : c_hi;
       // Winners in column order: every value above T, then the first `need`
       // equal to T; `sel` holds bit 4u + q for column u * 256 + 4 * lane + q.
+      // Ties are ranked in the one word where the `need` quota runs out:
+      // earlier words take all their ties, later ones none.
       uint32_t sel = 0, eq_before = 0, sel_before = 0;
       int32_t* wrow = a.win_out + (size_t)t * sh.k;
 #pragma unroll
@@ -326,16 +347,24 @@ __global__ __launch_bounds__(kPersistWaves * kWave) void k_sp_persistent_boost(B
           gt |= bv[4 * u + q] > T ? 1u << q : 0u;
           eq |= (T != 0 && bv[4 * u + q] == T) ? 1u << q : 0u;
         }
-        const uint32_t neq = (uint32_t)__popc(eq);
-        const uint32_t pre = eq_before + wave_prefix<3>(neq, lane);
-        uint32_t keep = need > pre ? need - pre : 0u, take = 0;
+        uint32_t take = 0;
+        if (eq_before < need) {
+          const uint32_t neq = (uint32_t)__popc(eq);
+          const uint32_t tot = wave_count<3>(neq);
+          if (eq_before + tot <= need) {
+            take = eq;
+          } else {
+            const uint32_t pre = eq_before + wave_prefix<3>(neq, lane);
+            uint32_t keep = need > pre ? need - pre : 0u;
 #pragma unroll
-        for (uint32_t q = 0; q < 4; ++q) {
-          const bool use = ((eq >> q) & 1u) && keep > 0;
-          take |= use ? 1u << q : 0u;
-          keep -= use ? 1u : 0u;
+            for (uint32_t q = 0; q < 4; ++q) {
+              const bool use = ((eq >> q) & 1u) && keep > 0;
+              take |= use ? 1u << q : 0u;
+              keep -= use ? 1u : 0u;
+            }
+          }
+          eq_before += tot;
         }
-        eq_before += wave_count<3>(neq);
         const uint32_t su = gt | take;
         sel |= su << (4 * u);
         if (gw == 0) {
@@ -360,10 +389,7 @@ __global__ __launch_bounds__(kPersistWaves * kWave) void k_sp_persistent_boost(B
       uint32_t changed = 0;
       if (a.learn) {
         // Learning on the own columns that won, with frame t.
-        uint32_t won = 0;
-#pragma unroll
-        for (uint32_t j = 0; j < CPW; ++j)
-          won |= (j < ncols && column_bit(sel, c_begin + j)) ? 1u << j : 0u;
+        const uint32_t won = own_bits(sel);
 #pragma unroll
         for (uint32_t r = 0; r < RW; ++r) {
           if ((won >> (r / RPC)) & (row_ok >> r) & 1u) {
@@ -373,7 +399,8 @@ __global__ __launch_bounds__(kPersistWaves * kWave) void k_sp_persistent_boost(B
             msk[r] = q >= sh.theta ? 1u << (i & 31u) : 0u;
           }
         }
-        // Duty cycles of every column, their maximum, the minimum, boosts.
+        // Duty cycles of every column, their maximum (17 bits, one ballot a
+        // bit from the top), the minimum, boosts.
         uint32_t mx = 0;
 #pragma unroll
         for (uint32_t i = 0; i < NC; ++i) {
@@ -383,32 +410,37 @@ __global__ __launch_bounds__(kPersistWaves * kWave) void k_sp_persistent_boost(B
                               b.period_log2);
           mx = max(mx, adc[i]);
         }
+        uint32_t wmx = 0;
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, off));
-        const uint32_t mn = (uint32_t)(((uint64_t)mx * b.min_pct_q16) >> 16);
-        // (max_boost - 256)(mn - a) / mn, exactly: a double estimate (within
-        // one of the quotient for numerators below 2^28), then corrected.
-        const double rmn = mn ? 1.0 / (double)mn : 0.0;
+        for (int bit = 16; bit >= 0; --bit) {
+          const uint32_t cand = wmx | (1u << bit);
+          if (__ballot(mx >= cand) != 0ull) wmx = cand;
+        }
+        const uint32_t mn = (uint32_t)(((uint64_t)wmx * b.min_pct_q16) >> 16);
+        // (max_boost - 256)(mn - a) / mn exactly, as (num * mg) >> (28 + l)
+        // with l = ceil(log2 mn) and mg = ceil(2^(28 + l) / mn): exact for
+        // numerators below 2^28 (the error term stays below 1 / mn), and num
+        // <= 3840 * 65536.
+        const uint32_t l = mn > 1 ? 32u - (uint32_t)__clz(mn - 1u) : 0u;
+        const uint64_t p2 = 1ull << (28 + l);
+        uint64_t mg = 0;
+        if (mn) {
+          // a double estimate of the ceiling, then the two integer checks
+          mg = (uint64_t)((double)p2 / (double)mn);
+          mg = mg * mn < p2 ? mg + 1u : mg;
+          mg = (mg - 1u) * mn >= p2 ? mg - 1u : mg;
+        }
         uint32_t raise = 0;
 #pragma unroll
         for (uint32_t i = 0; i < NC; ++i) {
-          uint32_t nb = 256u;
-          if (mn != 0 && adc[i] < mn) {
-            const uint32_t num = (b.max_boost_q8 - 256u) * (mn - adc[i]);
-            uint32_t qt = (uint32_t)((double)num * rmn);
-            qt = (uint64_t)qt * mn > num ? qt - 1u : qt;
-            qt = (uint64_t)(qt + 1u) * mn <= num ? qt + 1u : qt;
-            nb = 256u + qt;
-          }
-          bst[i] = nb;
+          const uint32_t num = (b.max_boost_q8 - 256u) * (mn - min(adc[i], mn));
+          const uint32_t qt = (uint32_t)(((uint64_t)num * mg) >> (28 + l));
+          bst[i] = 256u + qt;
           raise |= (odc[i] < mn) ? 1u << i : 0u;
         }
         // Permanence raise of the own columns whose overlap duty is below it.
         if (b.bump_q8) {
-          uint32_t up = 0;
-#pragma unroll
-          for (uint32_t j = 0; j < CPW; ++j)
-            up |= (j < ncols && column_bit(raise, c_begin + j)) ? 1u << j : 0u;
+          const uint32_t up = own_bits(raise);
 #pragma unroll
           for (uint32_t r = 0; r < RW; ++r) {
             if ((up >> (r / RPC)) & (row_ok >> r) & 1u) {

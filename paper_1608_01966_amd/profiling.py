@@ -29,6 +29,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = {
     "k_sp_persistent_w": ("sp_kernels.hip", "sp_device.h", "sp_internal.h"),
     "k_sp_persistent_local": ("sp_local.hip", "sp_device.h", "sp_internal.h"),
+    "k_sp_persistent_local2": ("sp_local.hip", "sp_device.h", "sp_internal.h"),
     "k_sp_persistent_boost": ("sp_boost.hip", "sp_device.h", "sp_internal.h"),
     "k_infer_gather": ("sp_infer.hip", "sp_device.h", "sp_internal.h"),
     "k_infer_gather_db": ("sp_infer.hip", "sp_device.h", "sp_internal.h"),

@@ -115,54 +115,82 @@ __device__ __forceinline__ uint32_t count_ge32(const uint32_t (&bv)[N], uint32_t
 }
 
 // T = the largest x >= 1 with #(value >= x) >= k (0 when fewer than k
-// values are positive), *c_hi = #(value >= T + 1); a gallop from `guess`,
-// then a binary search (the same search as the 16-bit packed form).
+// values are positive), *c_hi = #(value >= T + 1).  Boosted values are
+// overlaps times a boost in 1/256 units, and those near the threshold are
+// often whole multiples of 256 (unboosted columns), so the search runs in two
+// stages: the coarse threshold y (largest y with #(value >= 256 y) >= k) by
+// a gallop from guess / 256 and a binary search, then one count at 256 y + 1,
+// which settles T = 256 y whenever no value lies strictly between 256 y and
+// 256 (y + 1); only otherwise a binary search of the 255 values between.
 template <int N>
 __device__ __forceinline__ uint32_t topk_threshold32(const uint32_t (&bv)[N], uint32_t vmax,
                                                      uint32_t k, uint32_t guess,
                                                      uint32_t* c_hi_out) {
-  uint32_t lo = 0, hi = vmax, c_hi = 0;
-  const uint32_t g0 = min(max(guess, 1u), vmax);
-  const uint32_t c0 = count_ge32(bv, g0);
-  if (c0 >= k) {
-    lo = g0;
-    for (uint32_t step = 1; lo < hi; step <<= 1) {
-      const uint32_t x = hi - lo > step ? lo + step : hi;
-      const uint32_t cx = count_ge32(bv, x);
-      if (cx >= k) {
-        lo = x;
+  // Stage 1 over y, counting values >= y << 8; c_hi = #(value >= (hi + 1) << 8).
+  const uint32_t ymax = vmax >> 8;
+  uint32_t lo = 0, hi = ymax, c_hi = 0;
+  if (ymax > 0) {
+    const uint32_t g0 = min(max(guess >> 8, 1u), ymax);
+    const uint32_t c0 = count_ge32(bv, g0 << 8);
+    if (c0 >= k) {
+      lo = g0;
+      for (uint32_t step = 1; lo < hi; step <<= 1) {
+        const uint32_t y = hi - lo > step ? lo + step : hi;
+        const uint32_t cy = count_ge32(bv, y << 8);
+        if (cy >= k) {
+          lo = y;
+        } else {
+          hi = y - 1;
+          c_hi = cy;
+          break;
+        }
+      }
+    } else {
+      hi = g0 - 1;
+      c_hi = c0;
+      for (uint32_t step = 1; hi > 0; step <<= 1) {
+        const uint32_t y = hi >= step ? hi - step + 1 : 1u;
+        const uint32_t cy = count_ge32(bv, y << 8);
+        if (cy >= k) {
+          lo = y;
+          break;
+        }
+        hi = y - 1;
+        c_hi = cy;
+      }
+    }
+    while (lo < hi) {
+      const uint32_t mid = lo + (hi - lo + 1) / 2;
+      const uint32_t c = count_ge32(bv, mid << 8);
+      if (c >= k) {
+        lo = mid;
       } else {
-        hi = x - 1;
-        c_hi = cx;
-        break;
+        hi = mid - 1;
+        c_hi = c;
       }
     }
-  } else {
-    hi = g0 - 1;
-    c_hi = c0;
-    for (uint32_t step = 1; hi > 0; step <<= 1) {
-      const uint32_t x = hi >= step ? hi - step + 1 : 1u;
-      const uint32_t cx = count_ge32(bv, x);
-      if (cx >= k) {
-        lo = x;
-        break;
-      }
-      hi = x - 1;
-      c_hi = cx;
-    }
+  }  // (ymax == 0: every value is below 256 = (hi + 1) << 8, so c_hi = 0)
+  // Stage 2 in [base, base + 255]: #(value >= base) >= k (base >= 1) and
+  // #(value >= base + 256) = c_hi < k.
+  const uint32_t base = lo << 8;
+  const uint32_t c1 = count_ge32(bv, base + 1u);
+  if (c1 < k) {
+    *c_hi_out = c1;
+    return base;
   }
-  while (lo < hi) {
-    const uint32_t mid = lo + (hi - lo + 1) / 2;
+  uint32_t flo = base + 1u, fhi = min(base + 255u, vmax), fc = c_hi;
+  while (flo < fhi) {
+    const uint32_t mid = flo + (fhi - flo + 1) / 2;
     const uint32_t c = count_ge32(bv, mid);
     if (c >= k) {
-      lo = mid;
+      flo = mid;
     } else {
-      hi = mid - 1;
-      c_hi = c;
+      fhi = mid - 1;
+      fc = c;
     }
   }
-  *c_hi_out = c_hi;
-  return lo;
+  *c_hi_out = fc;
+  return flo;
 }
 
 template <int RPC, int NV, int RW>

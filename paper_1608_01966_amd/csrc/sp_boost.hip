@@ -284,9 +284,29 @@ __global__ __launch_bounds__(kPersistWaves * kWave) void k_sp_persistent_boost(B
     return r;
   };
 
+  // Frame wt's winners in column order from their bits (bit 4u + q of lane
+  // l: column u * 256 + 4l + q) and count, then the -1 padding; global wave 0
+  // writes them while the next frame's exchange is in flight.
+  auto write_winners = [&](uint32_t ws, uint32_t wn, uint32_t wt) {
+    int32_t* wr = a.win_out + (size_t)wt * sh.k;
+    uint32_t before = 0;
+#pragma unroll
+    for (uint32_t u = 0; u < NV; ++u) {
+      const uint32_t su = (ws >> (4 * u)) & 15u;
+      uint32_t pos = before + wave_prefix<3>((uint32_t)__popc(su), lane);
+#pragma unroll
+      for (uint32_t q = 0; q < 4; ++q)
+        if ((su >> q) & 1u) wr[pos++] = (int32_t)(u * 4 * kWave + 4 * lane + q);
+      before += wave_count<3>((uint32_t)__popc(su));
+    }
+    for (uint32_t i = wn + lane; i < sh.k; i += kWave) wr[i] = -1;
+  };
+
   auto run = [&](auto role) {
     constexpr bool POLL = decltype(role)::value;
     uint32_t w[RW], o[CPW];
+    uint32_t wsel = 0, wnsel = 0, wt = 0;  // global wave 0: winners not yet written
+    bool wpend = false;
     gather(0, w);
     overlaps((1u << CPW) - 1u, w, o);
     if (lane < CPW) pub[wave * CPW + lane] = lane_value(o, lane);
@@ -307,6 +327,7 @@ __global__ __launch_bounds__(kPersistWaves * kWave) void k_sp_persistent_boost(B
       uint32_t nx[RW], on[CPW];
       gather(t + 1, nx);
       overlaps((1u << CPW) - 1u, nx, on);  // speculation: no own column changes
+      if (gw == 0 && wpend) write_winners(wsel, wnsel, wt);
 
       uint64_t v[NV];
       if constexpr (POLL) {
@@ -365,8 +386,7 @@ __global__ __launch_bounds__(kPersistWaves * kWave) void k_sp_persistent_boost(B
       // equal to T; `sel` holds bit 4u + q for column u * 256 + 4 * lane + q.
       // Ties are ranked in the one word where the `need` quota runs out:
       // earlier words take all their ties, later ones none.
-      uint32_t sel = 0, eq_before = 0, sel_before = 0;
-      int32_t* wrow = a.win_out + (size_t)t * sh.k;
+      uint32_t sel = 0, eq_before = 0;
 #pragma unroll
       for (uint32_t u = 0; u < NV; ++u) {
         uint32_t gt = 0, eq = 0;
@@ -393,18 +413,13 @@ __global__ __launch_bounds__(kPersistWaves * kWave) void k_sp_persistent_boost(B
           }
           eq_before += tot;
         }
-        const uint32_t su = gt | take;
-        sel |= su << (4 * u);
-        if (gw == 0) {
-          uint32_t pos = sel_before + wave_prefix<3>((uint32_t)__popc(su), lane);
-#pragma unroll
-          for (uint32_t q = 0; q < 4; ++q)
-            if ((su >> q) & 1u) wrow[pos++] = (int32_t)(u * 4 * kWave + 4 * lane + q);
-          sel_before += wave_count<3>((uint32_t)__popc(su));
-        }
+        sel |= (gt | take) << (4 * u);
       }
       if (gw == 0) {
-        for (uint32_t i = nsel + lane; i < sh.k; i += kWave) wrow[i] = -1;
+        wsel = sel;
+        wnsel = nsel;
+        wt = t;
+        wpend = true;
         if (a.ov_out) {
 #pragma unroll
           for (uint32_t i = 0; i < NC; ++i) {
@@ -491,6 +506,7 @@ __global__ __launch_bounds__(kPersistWaves * kWave) void k_sp_persistent_boost(B
       if (lane < CPW) pub[wave * CPW + lane] = lane_value(o, lane);
       __syncthreads();
     }
+    if (!abort && gw == 0 && wpend) write_winners(wsel, wnsel, wt);
   };
   if (a.F > 0) {
     if (wave == 0)

@@ -41,6 +41,9 @@
  * (4 * (S * C + C) bytes) plus, when sp_infer gets no overlap buffer, an
  * [F][C] scratch, and on the first sp_step_boost the boost state
  * (13 C bytes, rounded up); sp_destroy frees or pools all of it.
+ * sp_step_many keeps two staging buffers per device for the library's
+ * lifetime (descriptors, and a packed copy of the launch's synapses, 4 bytes
+ * each, rebuilt by every launch), grown when a launch needs more.
  *
  * Streams: `stream` is a hipStream_t (NULL = the null stream).  Steps are
  * enqueued and return at once; results are valid once the stream has

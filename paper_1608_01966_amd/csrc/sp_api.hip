@@ -337,6 +337,9 @@ struct ManySlot {
   void* host = nullptr;
   void* dev = nullptr;
   size_t cap = 0;
+  // the launch's packed copy of its instances' synapses (device scratch)
+  void* mir = nullptr;
+  size_t mir_cap = 0;
   hipEvent_t done = nullptr;
 };
 
@@ -353,7 +356,7 @@ struct ManyCtx {
 std::mutex g_many_mu;
 ManyCtx g_many[16];
 
-int many_slot(int device, size_t bytes, ManySlot** out, int* index) {
+int many_slot(int device, size_t bytes, size_t mir_bytes, ManySlot** out, int* index) {
   if (device < 0 || device >= 16) return fail(SP_EDEVICE, "device %d out of range", device);
   ManyCtx& ctx = g_many[device];
   ctx.device = device;
@@ -382,6 +385,18 @@ int many_slot(int device, size_t bytes, ManySlot** out, int* index) {
       return fail(SP_ENOMEM, "many-instance staging allocation (%zu bytes)", cap);
     }
     sl.cap = cap;
+  }
+  if (sl.mir_cap < mir_bytes) {
+    if (sl.mir) (void)hipFree(sl.mir);
+    sl.mir = nullptr;
+    sl.mir_cap = 0;
+    const size_t cap = mir_bytes + mir_bytes / 4;
+    e = hipMalloc(&sl.mir, cap);
+    if (e != hipSuccess) {
+      sl.mir = nullptr;
+      return fail(SP_ENOMEM, "many-instance packed state allocation (%zu bytes)", cap);
+    }
+    sl.mir_cap = cap;
   }
   *out = &sl;
   return SP_OK;
@@ -465,9 +480,14 @@ int many_launch(sp_handle* const* hs, uint32_t n, const uint32_t* const* frames_
   tiles.reserve(ntiles);
   insts.reserve(nact);
   uint32_t spin_limit = kSpinLimit;
+  thread_local std::vector<size_t> mir_off;
+  mir_off.clear();
+  size_t mir_bytes = 0;
   for (uint32_t i = 0; i < n; ++i) {
     sp_handle* h = hs[i];
     if (num_frames[i] == 0) continue;
+    mir_off.push_back(mir_bytes);
+    mir_bytes = align_up(mir_bytes + sizeof(uint32_t) * (size_t)h->sh.C * h->sh.S, 256);
     const uint32_t id = (uint32_t)insts.size();
     htmsp::ManyInst in = {};
     in.idx = h->idx;
@@ -502,8 +522,10 @@ int many_launch(sp_handle* const* hs, uint32_t n, const uint32_t* const* frames_
   const size_t b_off = sizeof(uint32_t) * (grid + 1);
   ManySlot* sl = nullptr;
   int slot_index = 0;
-  int rc = many_slot(dev, b_err + b_insts + b_tasks + b_off, &sl, &slot_index);
+  int rc = many_slot(dev, b_err + b_insts + b_tasks + b_off, mir_bytes, &sl, &slot_index);
   if (rc) return rc;
+  for (size_t i = 0; i < insts.size(); ++i)
+    insts[i].mir = reinterpret_cast<uint32_t*>(static_cast<char*>(sl->mir) + mir_off[i]);
   char* hb = static_cast<char*>(sl->host);
   char* db = static_cast<char*>(sl->dev);
   memset(hb, 0, b_err);

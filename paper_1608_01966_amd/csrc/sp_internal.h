@@ -258,6 +258,7 @@ struct ManyInst {
   uint32_t* ovx;           // [C] tagged overlaps
   uint64_t* dec;           // decision word
   uint32_t* hist;          // [C] winner counts to add to, or null
+  uint32_t* mir;           // [C][S] launch scratch: min(idx, N - 1) << 9 | q of each synapse
   Shape sh;
   uint32_t F, step_base, guess;
   uint32_t smagic;         // ceil(2^32 / S), 0 for S = 1: floor(p / S) for p < 2^13

@@ -111,22 +111,19 @@ __device__ void tile_step(const ManyArgs& a, const ManyInst& in, uint32_t c0, ui
   const uint32_t m = in.smagic;
 
   const size_t p0 = (size_t)c0 * sh.S;
-  const HTMSP_G uint32_t* gidx = gbl(in.idx + p0);
   HTMSP_G float* gperm = gbl(in.perm + p0);
-  // loads without branches (past the tile: its last synapse, then ignored),
-  // so that all of them are in flight together
+  HTMSP_G uint32_t* gmir = gbl(in.mir + p0);
+  // One packed word per synapse (index << 9 | q, from the launch's packing
+  // pass); loads without branches (past the tile: its last synapse, then
+  // ignored), so that all of them are in flight together.
   uint32_t ix[kPerThread], q[kPerThread];
 #pragma unroll
-  for (uint32_t j = 0; j < kPerThread; ++j) {
-    const uint32_t p = min(tid + kManyThreads * j, nsyn - 1);
-    ix[j] = gidx[p];
-    q[j] = perm_to_q(gperm[p]);
-  }
+  for (uint32_t j = 0; j < kPerThread; ++j) ix[j] = gmir[min(tid + kManyThreads * j, nsyn - 1)];
 #pragma unroll
   for (uint32_t j = 0; j < kPerThread; ++j) {
     const bool v = tid + kManyThreads * j < nsyn;
-    ix[j] = v ? min(ix[j], sh.N - 1) : 0u;
-    q[j] = v ? q[j] : 0u;
+    q[j] = v ? ix[j] & 511u : 0u;
+    ix[j] = v ? ix[j] >> 9 : 0u;
   }
   // column cl of this tile won frame t - 1 (its overlap of that frame is the
   // one this tile published last step)
@@ -163,6 +160,7 @@ __device__ void tile_step(const ManyArgs& a, const ManyInst& in, uint32_t c0, ui
       if (won & (1u << j)) {
         q[j] = learn_q(q[j], input_bit(wp[j], ix[j]), sh);
         gperm[tid + kManyThreads * j] = q_to_perm(q[j]);
+        gmir[tid + kManyThreads * j] = (ix[j] << 9) | q[j];
       }
     }
   }
@@ -400,6 +398,19 @@ __global__ __launch_bounds__(kManyThreads, 2) void k_sp_many(ManyArgs a) {
   }
 
   // ---- tile workgroup ----
+  // The launch's packed copy of each tile's synapses, written by the thread
+  // that reads it in every step (same flat positions), so each step loads
+  // one word per synapse instead of an index and a permanence.
+  for (uint32_t j = 0; j < nt && t1 - t0 <= kMaxTileSlots; ++j) {
+    const ManyInst& in = s_inst[j];
+    const size_t p0 = (size_t)s_task[j].c0 * in.sh.S;
+    const uint32_t nsyn = (s_task[j].c1 - s_task[j].c0) * in.sh.S;
+    const HTMSP_G uint32_t* gidx = gbl(in.idx + p0);
+    const HTMSP_G float* gperm = gbl(in.perm + p0);
+    HTMSP_G uint32_t* gmir = gbl(in.mir + p0);
+    for (uint32_t p = tid; p < nsyn; p += kManyThreads)
+      gmir[p] = (min(gidx[p], in.sh.N - 1) << 9) | perm_to_q(gperm[p]);
+  }
   // Wave 0 looks at every tile at once (lane j: tile j) and takes the first
   // ready one at or after `rr`, so that no tile is passed over for long.
   // The decision words it looks at were loaded while the previous tile step

@@ -39,8 +39,11 @@
  * sp_create (or reuses one a destroyed handle left in the library's pool)
  * and, on the first sp_infer, the compacted connected lists
  * (4 * (S * C + C) bytes) plus, when sp_infer gets no overlap buffer, an
- * [F][C] scratch, and on the first sp_step_boost the boost state
- * (13 C bytes, rounded up); sp_destroy frees or pools all of it.
+ * [F][C] scratch, on the first sp_step_boost the boost state
+ * (13 C bytes, rounded up), and on the first sp_step that runs the
+ * persistent kernel a copy of the step's frames in pairs (8 bytes per
+ * input word per pair of frames, at most 64 MiB: longer steps run as
+ * several launches); sp_destroy frees or pools all of it.
  * sp_step_many keeps two staging buffers per device for the library's
  * lifetime (descriptors, and a packed copy of the launch's synapses, 4 bytes
  * each, rebuilt by every launch), grown when a launch needs more.
@@ -124,8 +127,10 @@ int sp_check_state(sp_handle* h, void* stream);
  * The frames run in one persistent launch that keeps the handle's synapse
  * state in registers (a group of columns per wave, one workgroup per CU, the
  * per-frame overlaps exchanged through device memory, two frames per
- * exchange); shapes it cannot hold (see sp_step_kernel) run as
- * sp_step_plain, with the same results.  A device-side failure of the
+ * exchange), after a short pass that copies the frames side by side in
+ * pairs; a step whose pairs exceed 64 MiB runs as several such launches.
+ * Shapes the kernel cannot hold (see sp_step_kernel) run as sp_step_plain,
+ * with the same results.  A device-side failure of the
  * persistent launch is reported by the next sp_sync. */
 int sp_step(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames, int learn,
             int32_t* overlaps_dev, int32_t* winners_dev, void* stream);

@@ -39,6 +39,10 @@ struct sp_handle {
   uint32_t many_steps; // steps this handle has taken through sp_step_many
   uint64_t frames_seen; // learning frames applied to the state (sp_get_state)
   uint64_t xchg_frames;
+  // the frames of persistent steps in pairs (PersistArgs::fpair), grown on
+  // use up to htmsp::kPairStageBytes
+  uint64_t* fpair;
+  uint32_t fpair_pairs;
   bool persistent;
   uint32_t grid, block, replicas;
   const void* pkernel;
@@ -220,6 +224,34 @@ int check_step_args(const sp_handle* h, const uint32_t* frames, uint32_t F, int3
   if (!win) return fail(SP_EINVAL, "winners is NULL");
   if (!aligned4(frames) || !aligned4(win) || (ov && !aligned4(ov)))
     return fail(SP_EINVAL, "frames, overlaps and winners must be 4-byte aligned");
+  return SP_OK;
+}
+
+// Frames one persistent launch of an F-frame step takes (even unless it is
+// the whole step), with the handle's paired-frame buffer grown to hold them.
+int pair_stage(sp_handle* h, uint32_t F, uint32_t* frames_per_launch) {
+  const size_t row = sizeof(uint64_t) * (size_t)h->sh.W;
+  const size_t cap = std::max<size_t>(1, htmsp::kPairStageBytes / row);
+  const size_t pairs = (size_t)F / 2 + (F & 1u);
+  const size_t need = std::min(cap, pairs);
+  if (h->fpair_pairs < need) {
+    const size_t want = std::min(cap, std::max(need, 2 * (size_t)h->fpair_pairs));
+    if (h->fpair) {
+      // (hipFree waits for the device, so no launch still reads the buffer)
+      const hipError_t e = hipFree(h->fpair);
+      h->fpair = nullptr;
+      h->fpair_pairs = 0;
+      if (e != hipSuccess) return hip_fail(e, "paired-frame buffer free");
+    }
+    const hipError_t e = hipMalloc(&h->fpair, row * want);
+    if (e != hipSuccess) {
+      h->fpair = nullptr;
+      return fail(SP_ENOMEM, "paired-frame buffer hipMalloc(%zu): %s", row * want,
+                  hipGetErrorString(e));
+    }
+    h->fpair_pairs = (uint32_t)want;
+  }
+  *frames_per_launch = (uint32_t)std::min<size_t>(2 * need, F);
   return SP_OK;
 }
 
@@ -709,30 +741,48 @@ int sp_step(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames, int l
   if (!h->persistent)
     return sp_step_plain(h, frames_dev, num_frames, learn, overlaps_dev, winners_dev, stream);
   DeviceScope ds(h->device);
-  IdleOnExit idle{h, static_cast<hipStream_t>(stream)};
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  IdleOnExit idle{h, s};
+  uint32_t chunk = 0;
+  rc = pair_stage(h, num_frames, &chunk);
+  if (rc) return rc;
+  const Shape& sh = h->sh;
   htmsp::PersistArgs a;
   a.idx = h->idx;
   a.perm = h->perm;
-  a.frames = frames_dev;
-  a.ov_out = overlaps_dev;
-  a.win_out = winners_dev;
+  a.fpair = h->fpair;
   a.xchg = h->xchg;
   a.err = h->err;
-  a.F = num_frames;
   a.learn = learn ? 1u : 0u;
-  a.frame_base = (uint32_t)h->xchg_frames;
   a.replicas = h->replicas;
-  a.spin_limit = h->stall_spins ? h->stall_spins : kSpinLimit;
-  a.stall = h->stall_spins ? 1u : 0u;
-  h->stall_spins = 0;
-  a.sh = h->sh;
+  a.sh = sh;
   void* args[] = {&a};
-  hipError_t e = hipLaunchCooperativeKernel(h->pkernel, dim3(h->grid), dim3(h->block), args, 0,
-                                            static_cast<hipStream_t>(stream));
-  if (e != hipSuccess) return hip_fail(e, "persistent step launch");
-  h->xchg_frames += (num_frames + 1) / 2;
+  // Launches of at most `chunk` frames, each after pairing its frames; the
+  // state goes back to idx/perm between them, so the results are those of
+  // one launch.
+  for (uint64_t t0 = 0; t0 < num_frames; t0 += chunk) {
+    const uint32_t F = (uint32_t)std::min<uint64_t>(chunk, num_frames - t0);
+    hipError_t e = htmsp::launch_pair_frames(frames_dev + t0 * sh.W, F, sh.W, h->fpair, s);
+    if (e != hipSuccess) {
+      note_learned(h, (uint32_t)t0, learn);
+      return hip_fail(e, "frame pairing launch");
+    }
+    a.ov_out = overlaps_dev ? overlaps_dev + t0 * sh.C : nullptr;
+    a.win_out = winners_dev + t0 * sh.k;
+    a.F = F;
+    a.frame_base = (uint32_t)h->xchg_frames;
+    a.spin_limit = h->stall_spins ? h->stall_spins : kSpinLimit;
+    a.stall = h->stall_spins ? 1u : 0u;
+    h->stall_spins = 0;
+    e = hipLaunchCooperativeKernel(h->pkernel, dim3(h->grid), dim3(h->block), args, 0, s);
+    if (e != hipSuccess) {
+      note_learned(h, (uint32_t)t0, learn);
+      return hip_fail(e, "persistent step launch");
+    }
+    h->xchg_frames += F / 2 + (F & 1u);
+  }
   note_learned(h, num_frames, learn);
-  return add_histogram(h, winners_dev, num_frames, static_cast<hipStream_t>(stream));
+  return add_histogram(h, winners_dev, num_frames, s);
 }
 
 }  // extern "C"
@@ -1422,6 +1472,7 @@ int sp_destroy(sp_handle* h) {
     if (e == hipSuccess && h->boost_mem) e = hipFree(h->boost_mem);
     if (e == hipSuccess && h->mfma_mask) e = hipFree(h->mfma_mask);
     if (e == hipSuccess && h->mfma_part) e = hipFree(h->mfma_part);
+    if (e == hipSuccess && h->fpair) e = hipFree(h->fpair);
     if (e == hipSuccess && !ws_give(h->device, h->ws, h->ws_bytes)) e = hipFree(h->ws);
     const hipError_t e2 = hipEventDestroy(h->idle);
     if (e == hipSuccess) e = e2;

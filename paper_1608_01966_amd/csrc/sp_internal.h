@@ -22,7 +22,9 @@ struct Shape {
 struct PersistArgs {
   const uint32_t* idx;
   float* perm;
-  const uint32_t* frames;
+  // [ceil(F/2)][W]: word i of frame 2p in the low half of entry p * W + i,
+  // of frame min(2p + 1, F - 1) in the high half (launch_pair_frames)
+  const uint64_t* fpair;
   int32_t* ov_out;    // [F][C] or null
   int32_t* win_out;   // [F][k]
   uint32_t* xchg;     // [replicas][2][arrays][entries] 16-bit tagged overlaps
@@ -121,6 +123,14 @@ hipError_t launch_overlap_plain(const uint32_t* idx, const float* perm, const ui
 // Overlaps lie in [0, vmax] (0: S).
 hipError_t launch_topk_plain(const int32_t* ov, int32_t* winners, const Shape& sh, hipStream_t s,
                              uint32_t frames = 1, uint32_t vmax = 0);
+// The frames of a step side by side in pairs (the layout of PersistArgs::fpair),
+// so that a kernel stepping two frames per exchange reads a synapse's input
+// words of both with one 64-bit load.
+hipError_t launch_pair_frames(const uint32_t* frames, uint32_t F, uint32_t W, uint64_t* out,
+                              hipStream_t s);
+// Bytes of paired frames one persistent launch reads at most; longer steps
+// run as several launches.
+constexpr size_t kPairStageBytes = size_t(64) << 20;
 hipError_t launch_learn_plain(const uint32_t* idx, float* perm, const uint32_t* frame,
                               const int32_t* winners, const Shape& sh, hipStream_t s);
 

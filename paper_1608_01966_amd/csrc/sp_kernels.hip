@@ -165,6 +165,23 @@ __global__ __launch_bounds__(256) void k_learn_plain(const uint32_t* __restrict_
   }
 }
 
+// Frames 2p and min(2p + 1, F - 1) side by side, one 64-bit entry per input
+// word: both frames read and the pair written once, coalesced.  Block
+// (x, y): words 1024 x ... 1024 x + 1023 of pair y.
+__global__ __launch_bounds__(256) void k_pair_frames(const uint32_t* __restrict__ frames,
+                                                     uint32_t F, uint32_t W, uint32_t p0,
+                                                     uint64_t* __restrict__ out) {
+  const uint32_t p = p0 + blockIdx.y;
+  const uint32_t* f0 = frames + (size_t)(2 * p) * W;
+  const uint32_t* f1 = frames + (size_t)min(2 * p + 1, F - 1) * W;
+  uint64_t* o = out + (size_t)p * W;
+#pragma unroll
+  for (uint32_t j = 0; j < 4; ++j) {
+    const uint32_t i = blockIdx.x * 1024 + j * 256 + threadIdx.x;
+    if (i < W) o[i] = f0[i] | ((uint64_t)f1[i] << 32);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Persistent multi-frame step.
 //
@@ -281,7 +298,23 @@ struct PollRole {
   static constexpr bool value = B;
 };
 
-template <int RPC, int NV, int RW>
+// Instances (RPC, NV, RW) whose wave 0 issues a pair's gathers only after
+// the workgroup's publish stores (PF below).  Each instance was timed both
+// ways over 1000 learning frames of the 960x540 input at one C x S that
+// lands on it: faster by 2-14 % at these, slower by up to 12 % or level at
+// every other one.  Whether the exchange reads wait for entries still on
+// their way or come back late depends on how the publish stores and the
+// gathers share the workgroup's memory pipeline, which the instance sets;
+// the results are the same either way.
+constexpr bool publish_first(int rpc, int nv, int rw) {
+  return (rpc == 2 && nv == 4 && rw == 4) || (rpc == 4 && nv == 4 && rw == 8) ||
+         (rpc == 1 && nv == 8 && rw == 4) || (rpc == 2 && nv == 8 && rw == 8) ||
+         (rpc == 8 && nv == 2 && rw == 8) || (rpc == 16 && nv == 4 && rw == 16) ||
+         (rpc == 1 && nv == 16 && rw == 8) || (rpc == 2 && nv == 16 && rw == 16) ||
+         (rpc == 4 && nv == 16 && rw == 16);
+}
+
+template <int RPC, int NV, int RW, bool PF = publish_first(RPC, NV, RW)>
 __global__ __launch_bounds__(kPersistWaves * kWave) void k_sp_persistent_w(PersistArgs a) {
   constexpr uint32_t CPW = RW / RPC;
   constexpr uint32_t CPAD = NV * 4 * kWave;        // entries per exchange array
@@ -292,12 +325,14 @@ __global__ __launch_bounds__(kPersistWaves * kWave) void k_sp_persistent_w(Persi
   __shared__ uint64_t xl[2][NARR][NV][kWave];
   __shared__ uint32_t pub[NARR][WGC];
   __shared__ uint32_t seen;
+  __shared__ uint32_t pubd[NARR];  // pairs each publishing wave has issued
   const Shape sh = a.sh;
   const uint32_t lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
   const uint32_t gw = blockIdx.x * kPersistWaves + wave;
   const uint32_t c_begin = gw * CPW;
   const uint32_t wg_begin = blockIdx.x * WGC;
   const uint32_t ncols = c_begin < sh.C ? min(CPW, sh.C - c_begin) : 0u;
+  if (threadIdx.x < NARR) pubd[threadIdx.x] = 0;
   if (threadIdx.x == 0) seen = 0;
 
   // State: idx << 9 | q, and the mask of the input bit while connected;
@@ -341,16 +376,18 @@ __global__ __launch_bounds__(kPersistWaves * kWave) void k_sp_persistent_w(Persi
     }
   };
 
-  // Input words of frames t and t + 1, each clamped to the last frame (a
-  // gather past the end is never used; issuing it unconditionally keeps the
-  // loads free of copies that would wait for them).
+  // Input words of frames t and t + 1 (t even), one 64-bit load per row
+  // from their pair, clamped to the last pair (a gather past the end is never
+  // used; issuing it unconditionally keeps the loads free of copies that
+  // would wait for them).  Random gathers cost the workgroup's L1 one tag
+  // lookup per distinct line per load; pairing halves the loads.
   auto gather = [&](uint32_t t, uint32_t (&x0)[RW], uint32_t (&x1)[RW]) {
-    const uint32_t* f0 = a.frames + (size_t)min(t, a.F - 1) * sh.W;
-    const uint32_t* f1 = a.frames + (size_t)min(t + 1, a.F - 1) * sh.W;
+    const uint64_t* fp = a.fpair + (size_t)min(t / 2, (a.F - 1) / 2) * sh.W;
 #pragma unroll
     for (uint32_t r = 0; r < RW; ++r) {
-      x0[r] = f0[wi[r]];
-      x1[r] = f1[wi[r]];
+      const uint64_t v = fp[wi[r]];
+      x0[r] = (uint32_t)v;
+      x1[r] = (uint32_t)(v >> 32);
     }
   };
 
@@ -415,6 +452,15 @@ __global__ __launch_bounds__(kPersistWaves * kWave) void k_sp_persistent_w(Persi
             store_word(x64w + (((size_t)(rr * 2 + slot) * NARR + arr) * CPAD + wg_begin) / 4 + lane,
                        word);
         }
+        if constexpr (PF) lds_release(&pubd[arr], pair + 1);
+      } else if constexpr (PF) {
+        // Wave 0 issues its gathers only after the workgroup's publish
+        // stores, which then reach the other workgroups sooner; its first
+        // read of the exchange moves later with them.  Waves 1..3 publish
+        // at the top of every pair they enter, so this wait always ends.
+        while (lds_acquire(&pubd[0]) <= pair || lds_acquire(&pubd[1]) <= pair ||
+               lds_acquire(&pubd[2]) <= pair)
+          __builtin_amdgcn_s_sleep(0);
       }
       // The next pair's input words, which arrive while the exchange is in flight.
       const uint32_t tn = t + 2;
@@ -659,6 +705,19 @@ hipError_t launch_learn_plain(const uint32_t* idx, float* perm, const uint32_t* 
                               const int32_t* winners, const Shape& sh, hipStream_t s) {
   hipLaunchKernelGGL(k_learn_plain, dim3(sh.k), dim3(256), 0, s, idx, perm, frame, winners, sh);
   return hipGetLastError();
+}
+
+hipError_t launch_pair_frames(const uint32_t* frames, uint32_t F, uint32_t W, uint64_t* out,
+                              hipStream_t s) {
+  const uint32_t P = (F + 1) / 2, bx = (W + 1023) / 1024;
+  constexpr uint32_t kMaxY = 65535;
+  for (uint32_t p0 = 0; p0 < P; p0 += kMaxY) {
+    hipLaunchKernelGGL(k_pair_frames, dim3(bx, std::min(kMaxY, P - p0)), dim3(256), 0, s, frames,
+                       F, W, p0, out);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace htmsp

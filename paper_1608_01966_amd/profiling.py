@@ -28,6 +28,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 # the source files each profiled kernel is compiled from
 KERNEL_SOURCES = {
     "k_sp_persistent_w": ("sp_kernels.hip", "sp_device.h", "sp_internal.h"),
+    "k_pair_frames": ("sp_kernels.hip", "sp_device.h", "sp_internal.h"),
     "k_sp_persistent_local": ("sp_local.hip", "sp_device.h", "sp_internal.h"),
     "k_sp_persistent_local2": ("sp_local.hip", "sp_device.h", "sp_internal.h"),
     "k_sp_persistent_boost": ("sp_boost.hip", "sp_device.h", "sp_internal.h"),

@@ -228,6 +228,15 @@ def test_max_input_bits():
     check(w)
 
 
+def test_step_longer_than_one_launch():
+    """At 2^23 input bits one persistent launch takes 64 frames (its paired
+    copy of the frames is bounded), so 151 frames run as launches of 64, 64
+    and 23 frames: the results must be those of stepping frame by frame."""
+    cfg = synth.sp_config(1 << 23, 256, 64, 2, 10)
+    w = synth.random_instance(31, cfg, frames=151, density=0.02)
+    check(w, expect_persistent=True)
+
+
 def test_zero_frames_is_noop():
     import torch
     w = synth.workload_plain_32x32(1)

@@ -644,10 +644,12 @@ def bench_local(args, torch, sp, synth):
     abytes = F * (frame_bytes(cfg) + 8 * C * S + 4 * C + C) + 12 * S * n_act
     achieved = abytes / (call_ms * 1e-3) / 1e9
     kname = pool.local_kernel_for(1024, 80)
+    # the two-frame kernel runs after the pass that pairs the frames
+    kspec = "k_pair_frames+" + kname if kname == "k_sp_persistent_local2" else kname
     traffic, traffic_bytes = (None, None)
     if kname != "plain" and F == 1000:
         traffic, traffic_bytes = measured_traffic(f"{kname}_960x540_1024c_256s_radius80.md",
-                                                  kname, call_ms)
+                                                  kspec, call_ms)
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -673,7 +675,7 @@ def bench_local(args, torch, sp, synth):
                    "frames_per_step": F, "active_per_frame": n_act / F, "path": "local"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": (kname if kname != "plain" else
+                     "kernel": (kspec.replace("+", " + ") if kname != "plain" else
                                 "k_overlap_plain + k_inhibit_local + k_learn_active"),
                      "kernel_ms_per_launch": call_ms, "algorithmic_bytes_per_launch": abytes,
                      "counter_bytes_per_launch": traffic_bytes},

@@ -1158,32 +1158,46 @@ int sp_step_local(sp_handle* h, const uint32_t* frames_dev, uint32_t num_frames,
   note_learned(h, num_frames, learn);
   const bool pair = h->lkernel2 && htmsp::persistent_local2_fits(sh.C, h->lwgc, grid_w, radius);
   if (h->lkernel) {
+    // The two-frame kernel reads the frames in pairs, in launches of at
+    // most `chunk` frames (the one-frame kernel takes all at once).
+    uint32_t chunk = num_frames;
+    if (pair) {
+      rc = pair_stage(h, num_frames, &chunk);
+      if (rc) return rc;
+    }
     htmsp::LocalArgs a;
     a.idx = h->idx;
     a.perm = h->perm;
-    a.frames = frames_dev;
-    a.ov_out = overlaps_dev;
-    a.active_out = active_dev;
+    a.fpair = h->fpair;
     a.xchg = pair ? h->xloc2 : h->xloc;
     a.err = h->err;
-    a.F = num_frames;
     a.learn = learn ? 1u : 0u;
-    a.frame_base = (uint32_t)(pair ? h->xloc2_pairs : h->xloc_frames);
     a.replicas = htmsp::kPersistReplicas;
-    a.spin_limit = h->stall_spins ? h->stall_spins : kSpinLimit;
-    a.stall = h->stall_spins ? 1u : 0u;
-    h->stall_spins = 0;
     a.grid_w = grid_w;
     a.radius = radius;
     a.sh = sh;
     void* args[] = {&a};
-    hipError_t e = hipLaunchCooperativeKernel(pair ? h->lkernel2 : h->lkernel, dim3(h->lgrid),
-                                              dim3(htmsp::kPersistWaves * 64), args, 0, s);
-    if (e != hipSuccess) return hip_fail(e, "persistent local step launch");
-    if (pair)
-      h->xloc2_pairs += (num_frames + 1) / 2;
-    else
-      h->xloc_frames += num_frames;
+    for (uint64_t t0 = 0; t0 < num_frames; t0 += chunk) {
+      const uint32_t F = (uint32_t)std::min<uint64_t>(chunk, num_frames - t0);
+      hipError_t e = hipSuccess;
+      if (pair) e = htmsp::launch_pair_frames(frames_dev + t0 * sh.W, F, sh.W, h->fpair, s);
+      if (e != hipSuccess) return hip_fail(e, "frame pairing launch");
+      a.frames = frames_dev + t0 * sh.W;
+      a.ov_out = overlaps_dev ? overlaps_dev + t0 * sh.C : nullptr;
+      a.active_out = active_dev + t0 * sh.C;
+      a.F = F;
+      a.frame_base = (uint32_t)(pair ? h->xloc2_pairs : h->xloc_frames);
+      a.spin_limit = h->stall_spins ? h->stall_spins : kSpinLimit;
+      a.stall = h->stall_spins ? 1u : 0u;
+      h->stall_spins = 0;
+      e = hipLaunchCooperativeKernel(pair ? h->lkernel2 : h->lkernel, dim3(h->lgrid),
+                                     dim3(htmsp::kPersistWaves * 64), args, 0, s);
+      if (e != hipSuccess) return hip_fail(e, "persistent local step launch");
+      if (pair)
+        h->xloc2_pairs += F / 2 + (F & 1u);
+      else
+        h->xloc_frames += F;
+    }
     return add_histogram_active(h, active_dev, num_frames, s);
   }
   for (uint32_t t = 0; t < num_frames; ++t) {

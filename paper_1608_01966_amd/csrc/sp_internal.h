@@ -56,7 +56,8 @@ uint32_t persistent_exchange_entries(uint32_t C);
 struct LocalArgs {
   const uint32_t* idx;
   float* perm;
-  const uint32_t* frames;
+  const uint32_t* frames;    // the one-frame kernel
+  const uint64_t* fpair;     // the two-frame kernel: as PersistArgs::fpair
   int32_t* ov_out;     // [F][C] or null
   uint8_t* active_out; // [F][C]
   uint64_t* xchg;      // [replicas][2][entries / 4] tagged overlaps

@@ -434,7 +434,15 @@ __device__ __forceinline__ bool local_active(uint32_t dx, uint32_t dy, uint32_t 
 // exactly those of stepping the frames one by one.  Exchange layout, tags,
 // poller, publishers and abort are those of the global two-frame kernel, in
 // the local pair region of the workspace with its own exchange counter.
-template <int RPC, int NV, int RW>
+// Instances of the two-frame local step whose wave 0 gathers only after the
+// workgroup's publish stores (as publish_first for the global step).  Timed
+// both ways over 1000 learning frames of the 960x540 input (1-D grid, radius
+// 80) at 256 x 32, 1024 x 64, 1024 x 256, 512 x 512, 2048 x 128 and
+// 4096 x 64: faster by 3-12 % wherever a lane holds two or more exchange
+// words, 8 % slower at one.
+constexpr bool local2_publish_first(int, int nv, int) { return nv >= 2; }
+
+template <int RPC, int NV, int RW, bool PF = local2_publish_first(RPC, NV, RW)>
 __global__ __launch_bounds__(kPersistWaves * kWave) void k_sp_persistent_local2(LocalArgs a) {
   constexpr uint32_t CPW = RW / RPC;
   constexpr uint32_t CPAD = NV * 4 * kWave;      // entries per exchange array
@@ -449,6 +457,7 @@ __global__ __launch_bounds__(kPersistWaves * kWave) void k_sp_persistent_local2(
   __shared__ uint32_t nhalo;
   __shared__ uint32_t pub[NARR][WGC];
   __shared__ uint32_t seen;
+  __shared__ uint32_t pubd[NARR];  // pairs each publishing wave has issued
   const Shape sh = a.sh;
   const uint32_t lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
   const uint32_t gw = blockIdx.x * kPersistWaves + wave;
@@ -457,6 +466,7 @@ __global__ __launch_bounds__(kPersistWaves * kWave) void k_sp_persistent_local2(
   const uint32_t ncols = c_begin < sh.C ? min(CPW, sh.C - c_begin) : 0u;
   const uint32_t rows = (sh.C + a.grid_w - 1) / a.grid_w;
   const bool mine = lane < ncols;
+  if (threadIdx.x < NARR) pubd[threadIdx.x] = 0;
   if (threadIdx.x == 0) seen = 0;
 
   // The halo box (rows hy0..hy0+bh-1, grid columns hx0..hx0+bw-1): the
@@ -503,14 +513,15 @@ __global__ __launch_bounds__(kPersistWaves * kWave) void k_sp_persistent_local2(
       pub[2][wave * CPW + lane] = lane_value(oW, lane);
     }
   };
-  // Input words of frames t and t + 1 (clamped to the last frame).
+  // Input words of frames t and t + 1 (t even), one 64-bit load per row
+  // from their pair (clamped to the last pair).
   auto gather = [&](uint32_t t, uint32_t (&x0)[RW], uint32_t (&x1)[RW]) {
-    const uint32_t* f0 = a.frames + (size_t)min(t, a.F - 1) * sh.W;
-    const uint32_t* f1 = a.frames + (size_t)min(t + 1, a.F - 1) * sh.W;
+    const uint64_t* fp = a.fpair + (size_t)min(t / 2, (a.F - 1) / 2) * sh.W;
 #pragma unroll
     for (uint32_t r = 0; r < RW; ++r) {
-      x0[r] = f0[wi[r]];
-      x1[r] = f1[wi[r]];
+      const uint64_t v = fp[wi[r]];
+      x0[r] = (uint32_t)v;
+      x1[r] = (uint32_t)(v >> 32);
     }
   };
   // Frame t's overlap, the state after learning frame t, and frame t + 1's
@@ -599,6 +610,12 @@ __global__ __launch_bounds__(kPersistWaves * kWave) void k_sp_persistent_local2(
             store_word(x64w + (((size_t)(rr * 2 + slot) * NARR + arr) * CPAD + wg_begin) / 4 + lane,
                        word);
         }
+        if constexpr (PF) lds_release(&pubd[arr], pair + 1);
+      } else if constexpr (PF) {
+        // (waves 1..3 publish at the top of every pair they enter)
+        while (lds_acquire(&pubd[0]) <= pair || lds_acquire(&pubd[1]) <= pair ||
+               lds_acquire(&pubd[2]) <= pair)
+          __builtin_amdgcn_s_sleep(0);
       }
       const uint32_t tn = t + 2;
       const bool has_next = tn < a.F;

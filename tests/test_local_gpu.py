@@ -257,3 +257,28 @@ def test_step_local_adaptive(case, learn):
     if learn and name != "one_row_grid":
         assert len(set(e_radii.tolist())) > 1, "the radius should move on this workload"
     pool.close()
+
+
+def test_step_local_longer_than_one_launch():
+    """At 2^23 input bits one launch of the two-frame local kernel takes 64
+    frames (its paired copy of the frames is bounded): 151 frames run as
+    launches of 64, 64 and 23 frames, with the results of one frame at a
+    time."""
+    import torch
+    cfg = synth.sp_config(1 << 23, 256, 64, 2, 3)
+    w = synth.random_instance(41, cfg, frames=151, density=0.02)
+    pool = sp.SpatialPooler(cfg, w.idx, w.perm)
+    assert pool.local_kernel_for(16, 2) == "k_sp_persistent_local2"
+    frames = torch.from_numpy(np.ascontiguousarray(w.frames).view(np.int32)).cuda()
+    F, C = w.frames.shape[0], cfg["num_columns"]
+    ov = torch.empty((F, C), dtype=torch.int32, device="cuda")
+    act = torch.empty((F, C), dtype=torch.uint8, device="cuda")
+    sp.sp_step_local(pool.handle, cfg, frames, True, 16, 2, ov, act)
+    pool.sync()
+    perm = pool.perm.cpu().numpy()
+    pool.close()
+    e_ov, e_act, e_perm = oracle.run_local(cfg, w.idx, w.perm, w.frames, 16, 2, 3)
+    assert np.array_equal(ov.cpu().numpy(), e_ov)
+    assert np.array_equal(act.cpu().numpy(), e_act)
+    assert np.array_equal(perm.astype(np.float64), e_perm)
+

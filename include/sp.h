@@ -50,7 +50,10 @@
  *
  * Streams: `stream` is a hipStream_t (NULL = the null stream).  Steps are
  * enqueued and return at once; results are valid once the stream has
- * synchronised.  A handle must not be used by two calls at the same time.
+ * synchronised.  A handle must not be used by two calls at the same time,
+ * and its calls must be ordered on the device (one stream, or streams the
+ * caller synchronises between calls): each call reuses the handle's state,
+ * workspace and buffers.
  *
  * Errors: every call returns SP_OK (0) or a negative sp_status; argument and
  * configuration checks happen on the host before anything is enqueued, and

@@ -19,10 +19,11 @@
 // nearest edge column, so border repetition needs no special case.  When
 // the output width is a multiple of 32 (rows start on word boundaries), a
 // strip's output width is a multiple of 32 too (512 threads: 480 columns at
-// the largest window, two strips for a 960-wide frame): every wave leaves
-// its row ballot in LDS and, after the next row's barrier, a thread per
-// output word assembles and stores the word once, so each word is written
-// by one store and nothing is cleared first.  Other widths OR each wave's
+// the largest window, two strips for a 960-wide frame): two output rows
+// share each barrier, every wave leaves its ballots of both in LDS and,
+// after the next barrier, a thread per output word assembles and stores
+// each word once, so each word is written by one store and nothing is
+// cleared first.  Other widths OR each wave's
 // 64-lane ballot into the (zeroed) output words it covers, which makes any
 // width and strip boundary correct.  Bands of one frame share an XCD (block
 // ids equal modulo 8), so the halo rows two bands both read come from L2.
@@ -62,8 +63,12 @@ __global__ __launch_bounds__(THREADS) void k_encode(const uint8_t* __restrict__ 
   constexpr int R = B / 2;
   constexpr uint32_t TW = strip_width<B, THREADS, WORDS>();  // output columns per strip
   constexpr uint32_t kWaves = THREADS / kWave;
-  __shared__ uint32_t vrow[2][THREADS];
-  __shared__ uint64_t bal[2][WORDS ? kWaves : 1];
+  // Output rows per barrier: two where every word is stored whole (their
+  // vertical sums and ballots side by side in LDS), one where waves OR
+  // their ballots into the output.
+  constexpr int RPB = WORDS ? 2 : 1;
+  __shared__ uint32_t vrow[2][RPB][THREADS];
+  __shared__ uint64_t bal[2][RPB][WORDS ? kWaves : 1];
   const uint32_t strips = (e.w + TW - 1) / TW;
   const uint32_t bands = (e.h + kBandRows - 1) / kBandRows;
   const uint32_t per = 8 * strips * bands;
@@ -118,14 +123,14 @@ __global__ __launch_bounds__(THREADS) void k_encode(const uint8_t* __restrict__ 
   uint32_t* dst = out + (size_t)f * e.words;
   uint32_t buf = 0;
   // WORDS: word j of output row `row` of this strip from the ballots in
-  // bal[b] (bit t of the concatenated ballots is thread t's column).
-  auto flush = [&](uint32_t row, uint32_t b) {
+  // bal[b][r] (bit t of the concatenated ballots is thread t's column).
+  auto flush = [&](uint32_t row, uint32_t b, int r) {
     if constexpr (WORDS) {
       const uint32_t j = tid;
       if (row < y1 && j < TW / 32 && strip * TW + 32 * j < e.w) {
         const uint32_t start = (uint32_t)R + 32 * j, q = start >> 6, o = start & 63u;
-        uint64_t v = bal[b][q] >> o;
-        if (o > 32) v |= bal[b][q + 1] << (64 - o);
+        uint64_t v = bal[b][r][q] >> o;
+        if (o > 32) v |= bal[b][r][q + 1] << (64 - o);
         dst[((size_t)row * e.w + strip * TW) / 32 + j] = (uint32_t)v;
       }
     }
@@ -149,38 +154,49 @@ __global__ __launch_bounds__(THREADS) void k_encode(const uint8_t* __restrict__ 
   }
   for (uint32_t yb = y0; yb < y1; yb += kAhead) {
 #pragma unroll
-  for (int k = 0; k < kAhead; ++k) {
-    const uint32_t y = yb + k;
+  for (int k0 = 0; k0 < kAhead; k0 += RPB) {
+    uint32_t cen[RPB];  // each row's own gray value
 #pragma unroll
-    for (int i = 0; i < B - 1; ++i) win[i] = win[i + 1];
-    if constexpr (ONE) {
-      win[B - 1] = (4899u * pr[k] + 9617u * pg[k] + 1868u * pb[k] + 8192u) >> 14;
-      issue(k, y + R + kAhead);
-    } else {
-      win[B - 1] = gray((uint32_t)min((int)y + R, (int)e.h - 1));
+    for (int r = 0; r < RPB; ++r) {
+      const int k = k0 + r;
+      const uint32_t y = yb + k;
+#pragma unroll
+      for (int i = 0; i < B - 1; ++i) win[i] = win[i + 1];
+      if constexpr (ONE) {
+        win[B - 1] = (4899u * pr[k] + 9617u * pg[k] + 1868u * pb[k] + 8192u) >> 14;
+        issue(k, y + R + kAhead);
+      } else {
+        win[B - 1] = gray((uint32_t)min((int)y + R, (int)e.h - 1));
+      }
+      uint32_t v = 0;
+#pragma unroll
+      for (int i = 0; i < B; ++i) v += wt[i] * win[i];
+      vrow[buf][r][tid] = v;
+      cen[r] = win[R];
     }
-    uint32_t v = 0;
-#pragma unroll
-    for (int i = 0; i < B; ++i) v += wt[i] * win[i];
-    vrow[buf][tid] = v;
-    // The row of vertical sums (and the previous row's ballots) are the only
-    // thing the barrier orders: wait for LDS only, so the row loads issued
-    // ahead stay in flight across it.
+    // The rows of vertical sums (and the previous rows' ballots) are the
+    // only thing the barrier orders: wait for LDS only, so the row loads
+    // issued ahead stay in flight across it.
     asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
-    if (y > y0) flush(y - 1, buf ^ 1u);
+    if (yb + k0 > y0) {
+#pragma unroll
+      for (int r = 0; r < RPB; ++r) flush(yb + k0 - RPB + r, buf ^ 1u, r);
+    }
+#pragma unroll
+    for (int r = 0; r < RPB; ++r) {
+    const uint32_t y = yb + k0 + r;
     bool on = false;
     if (out_col && y < y1) {
-      const uint32_t* vr = &vrow[buf][tid - R];
+      const uint32_t* vr = &vrow[buf][r][tid - R];
       uint32_t s = 0;
 #pragma unroll
       for (int j = 0; j < B; ++j) s += wt[j] * vr[j];
       const int mean = (int)((s + (1u << (kShift - 1))) >> kShift);
-      on = (int)win[R] > mean - e.offset;
+      on = (int)cen[r] > mean - e.offset;
     }
     uint64_t bits = __ballot(on);
     if constexpr (WORDS) {
-      if (lane == 0) bal[buf][wave] = bits;
-      buf ^= 1u;
+      if (lane == 0) bal[buf][r][wave] = bits;
       continue;
     }
     // the wave's 64 columns start at xs; output bit y * w + xs + lane
@@ -198,14 +214,16 @@ __global__ __launch_bounds__(THREADS) void k_encode(const uint8_t* __restrict__ 
       if (lane == 2 && o) part = (uint32_t)(bits >> (64 - o));
       if (part && wi + lane < e.words) atomicOr(&dst[wi + lane], part);
     }
+    }
     buf ^= 1u;
   }
   }
   if constexpr (WORDS) {
-    // the band's last row: its ballots are in bal[buf ^ 1]
+    // the band's last rows: their ballots are in bal[buf ^ 1]
     asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
     const uint32_t rows = (y1 - y0 + kAhead - 1) / kAhead * kAhead;
-    flush(y0 + rows - 1, buf ^ 1u);
+#pragma unroll
+    for (int r = 0; r < RPB; ++r) flush(y0 + rows - RPB + r, buf ^ 1u, r);
   }
 }
 
